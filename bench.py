@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of exact learned-sparse top-k retrieval on one MI355X.
+
+Workload (default): 8.8M synthetic passages shaped like the paper's MS MARCO +
+SPLADE collection (about 1.06 B postings), one batch of 500 queries, exact
+top-1000 per query, fp32 posting weights. A step is one full search of the
+batch (scoring + selection), with the index, the batch and the workspace
+resident in HBM before the timed region starts.
+
+Prints ONE JSON line (rank 0) with QPS, the roofline of the dominant kernel
+(scoring; HIP events around its launches, algorithmic bytes = the postings of
+every query term plus one write of each score array), the CPU oracle baseline
+on a bounded sample of the same batch, and the other precision forms.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QPS @8.8M docs top-1000 (fp32 vs uint8/bf16, batched); HBM GB/s %; p50/p99 ms"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+WEIGHT_BYTES = {"fp32": 4, "bf16": 2, "u8": 1}
+DTYPE = {"fp32": "f32", "bf16": "bf16+f64", "u8": "u8/i32"}
+T0 = time.time()
+
+
+def log(msg):
+    print("[bench %6.1fs] %s" % (time.time() - T0, msg), file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="full-8.8m")
+    ap.add_argument("--n-docs", type=int, default=0, help="override the collection size")
+    ap.add_argument("--batch", type=int, default=0, help="override the number of queries")
+    ap.add_argument("--k", type=int, default=1000)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "u8"])
+    ap.add_argument("--kernel", default="tiled", choices=["tiled", "atomic", "docpar"])
+    ap.add_argument("--tile-docs", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--forms", default="u8,bf16", help="other precisions to time (comma list, or 'none')")
+    ap.add_argument("--cpu-sample", type=int, default=16, help="queries timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--profile", action="store_true", help="main form only, no CPU leg (for profiler runs)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(df, queries, n_docs, wbytes):
+    """Per-query postings of the query's terms (doc id + weight) and one score-array write / read."""
+    p_q = np.array([int(df[queries.row(i)[0]].sum()) for i in range(queries.n_rows)], dtype=np.int64)
+    score_kernel = int(p_q.sum()) * (4 + wbytes) + queries.n_rows * n_docs * 4
+    step = score_kernel + queries.n_rows * n_docs * 4
+    return p_q, score_kernel, step
+
+
+def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_forward=False):
+    idx = gs.Index.from_rows(docs, precision, keep_forward=keep_forward)
+    batch = idx.batch(queries, k)
+    nq = queries.n_rows
+    ws = idx.workspace(nq, opts)
+    ids = torch.empty((nq, batch.k_max), dtype=torch.int32, device="cuda")
+    sc = torch.empty((nq, batch.k_max), dtype=gs.SCORE_DTYPES[idx.precision], device="cuda")
+    for _ in range(warmup):
+        idx.search(batch, ws, opts, out=(ids, sc))
+    torch.cuda.synchronize()
+    gs.timing_read()
+    gs.timing_enable(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        idx.search(batch, ws, opts, out=(ids, sc))
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    gs.timing_enable(False)
+    t = gs.timing_read()
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    total_ms = ev[0].elapsed_time(ev[steps])
+    diag = batch.diagnostics()
+    res = {"ids": ids.cpu().numpy(), "scores": sc.cpu().numpy(), "total_ms": total_ms, "step_ms": step_ms,
+           "timing": t, "diag": diag, "device_bytes": int(idx.info().device_bytes), "ws_bytes": ws.numel()}
+    del ws, ids, sc
+    batch.close()
+    idx.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workload
+    import paper_2606_26441_amd as gs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = workload.WORKLOADS[args.workload]
+    n_docs = args.n_docs or w.n_docs
+    nq = args.batch or w.n_queries
+    log("synthesising %d docs (%s) ..." % (n_docs, w.name))
+    docs = workload.make_collection(w, n_docs=n_docs)
+    queries = workload.make_queries(w, n=nq)
+    log("collection: %d postings; queries: %d (mean nnz %.1f)" % (docs.nnz, nq, queries.nnz / max(nq, 1)))
+    df = np.bincount(docs.terms, minlength=docs.vocab)
+    opts = gs.make_opts(args.kernel, tile_docs=args.tile_docs, chunk=args.chunk)
+
+    log("main form: %s / %s, %d warmup + %d timed steps" % (args.precision, args.kernel, args.warmup, args.steps))
+    main_res = time_form(gs, torch, docs, queries, args.k, args.precision, opts, args.steps, args.warmup,
+                         keep_forward=(args.kernel == "docpar"))
+    p_q, score_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision])
+    ms_per_step = main_res["total_ms"] / args.steps
+    qps = nq * args.steps / (main_res["total_ms"] / 1e3)
+    t = main_res["timing"]
+    score_ms = t["score_ms"] / max(t["score_launches"], 1)
+    select_ms = t["select_ms"] / max(t["select_launches"], 1)
+    achieved = score_bytes / (score_ms / 1e3) / 1e9
+    log("QPS %.1f  ms/step %.2f  score %.2f ms  select %.2f ms  score kernel %.0f GB/s"
+        % (qps, ms_per_step, score_ms, select_ms, achieved))
+
+    out = {
+        "metric": METRIC,
+        "value": round(qps, 2),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic (seeded Zipf(1.1)/Poisson/lognormal stand-in for MS MARCO + SPLADE)",
+        "config": {"workload": w.name, "n_docs": n_docs, "postings": docs.nnz, "batch": nq, "k": args.k,
+                   "precision": args.precision, "kernel": args.kernel, "tile_docs": args.tile_docs or 16384,
+                   "chunk": args.chunk or 256, "query_nnz_mean": round(queries.nnz / max(nq, 1), 2),
+                   "postings_per_query_mean": int(p_q.mean())},
+        "roofline": {"bound": "hbm", "kernel": "k_score_tiled" if args.kernel == "tiled" else "score_" + args.kernel,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": score_bytes, "launch_ms": round(score_ms, 4),
+                     "queries_per_launch": nq},
+        "step": {"p50_ms": round(float(np.percentile(main_res["step_ms"], 50)), 3),
+                 "p99_ms": round(float(np.percentile(main_res["step_ms"], 99)), 3),
+                 "score_ms": round(score_ms, 3), "select_ms": round(select_ms, 3),
+                 "hbm_frac_whole_step": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "memory": {"index_bytes": main_res["device_bytes"], "workspace_bytes": main_res["ws_bytes"]},
+        "selection": {"candidates_mean": float(main_res["diag"][:, 0].mean()),
+                      "refine_passes_max": int(main_res["diag"][:, 1].max()),
+                      "overflow": int(main_res["diag"][:, 3].max())},
+    }
+
+    forms = {}
+    if not args.profile and args.forms != "none":
+        for prec in [f for f in args.forms.split(",") if f and f != args.precision]:
+            log("form %s ..." % prec)
+            r = time_form(gs, torch, docs, queries, args.k, prec, opts, max(3, args.steps // 2), 1)
+            ms = r["total_ms"] / max(3, args.steps // 2)
+            t = r["timing"]
+            forms[prec] = {"qps": round(nq / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
+                           "score_ms": round(t["score_ms"] / max(t["score_launches"], 1), 3),
+                           "select_ms": round(t["select_ms"] / max(t["select_launches"], 1), 3),
+                           "index_bytes": r["device_bytes"],
+                           "overflow": int(r["diag"][:, 3].max())}
+            forms[prec]["_res"] = r
+            log("form %s: QPS %.1f" % (prec, forms[prec]["qps"]))
+
+    if not args.profile and args.cpu_sample > 0:
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity_rules import check_exact_f64, check_exact_int, check_fp32
+
+        s = min(args.cpu_sample, nq)
+        sample = queries.subset(np.arange(s))
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+        log("CPU oracle on %d queries with %d threads ..." % (s, threads))
+        t0 = time.time()
+        rid, rsc = oracle.topk_f64(docs, sample, args.k, n_threads=threads)
+        cpu_s = time.time() - t0
+        out["cpu_baseline"] = {"value": round(s / cpu_s, 4), "unit": "queries/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "first %d of the %d queries, full %d-doc collection, exact fp64 top-%d "
+                                         "with full sort; %.1f s wall" % (s, nq, n_docs, args.k, cpu_s)}
+        # full-size parity of the timed launch configuration on the same sample
+        checked = {}
+        try:
+            for q in range(s):
+                t_, w_ = queries.row(q)
+                if args.precision == "fp32":
+                    check_fp32(docs, t_, w_, main_res["ids"][q], main_res["scores"][q], rid[q], rsc[q], args.k)
+            checked[args.precision] = "ok (%d queries)" % s
+            if "bf16" in forms:
+                r = forms["bf16"]["_res"]
+                for q in range(s):
+                    check_exact_f64(r["ids"][q], r["scores"][q], rid[q], rsc[q])
+                checked["bf16"] = "ids and fp64 scores identical (%d queries)" % s
+            if "u8" in forms:
+                s8 = min(4, s)
+                rid8, rsc8 = oracle.topk_i64(docs, queries.subset(np.arange(s8)), args.k, n_threads=threads)
+                r = forms["u8"]["_res"]
+                for q in range(s8):
+                    check_exact_int(r["ids"][q], r["scores"][q], rid8[q], rsc8[q])
+                checked["u8"] = "bit-exact (%d queries)" % s8
+        except AssertionError as e:
+            checked["error"] = str(e)[:200]
+        out["parity_sample"] = checked
+        log("parity: %s" % checked)
+    for f in forms.values():
+        f.pop("_res", None)
+    if forms:
+        out["forms"] = forms
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

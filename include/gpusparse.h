@@ -1,0 +1,240 @@
+/*
+ * gpusparse.h - exact learned-sparse retrieval on one MI355X (gfx950).
+ *
+ * C ABI of libgpusparse.so. What it computes is the paper's scoring method
+ * (GPUSparse, "GPU-Accelerated Learned Sparse Retrieval with Parallel Inverted
+ * Indices"):
+ *
+ *   score(q, d) = sum over the query's terms t of w_q(t) * w_d(t)      (Sec. 2.1; Sec. 4.1, first eq.)
+ *
+ * evaluated for every document through a term-major inverted index (Sec. 3.2)
+ * by scatter-adding w_q(t) * w_d(t) into one score array per query
+ * (Sec. 4.1, second eq.; Sec. 4.2), followed by an exact per-query top-k.
+ * Nothing is pruned (Sec. 4.3).
+ *
+ * Conventions for every entry point:
+ *  - Return value: GS_OK (0) or a negative gs_status. On error no output
+ *    buffer is written and gs_last_error() holds a message for the calling
+ *    thread.
+ *  - "host" pointers are read during the call only and stay owned by the
+ *    caller. "device" pointers are HIP device memory owned by the caller
+ *    (for example torch tensors); the library never frees them.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the legacy default
+ *    stream). Device work is enqueued on it; calls documented as
+ *    "asynchronous" return before the device finishes.
+ *  - Ranking order: score descending, then doc id ascending. Row q of a
+ *    result holds min(k[q], n_docs) entries; the remaining slots up to k_max
+ *    are id -1 with score 0. Documents sharing no term with the query have
+ *    score 0 and are ranked like any other document.
+ */
+#ifndef GPUSPARSE_H
+#define GPUSPARSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gs_index_s* gs_index;
+typedef struct gs_batch_s* gs_batch;
+
+enum gs_status {
+    GS_OK = 0,
+    GS_EINVAL = -1,       /* malformed input (see each call) */
+    GS_ENOMEM = -2,       /* host or device allocation failed */
+    GS_EHIP = -3,         /* a HIP runtime call failed */
+    GS_ECAPACITY = -4,    /* workspace or output too small */
+    GS_EUNSUPPORTED = -5  /* option not available for this index */
+};
+
+/* Posting-weight storage (the paper stores fp32, Sec. 3.1; compressed
+ * posting scores are its future work (2), Sec. 8). */
+enum gs_precision {
+    GS_FP32 = 0, /* fp32 weights, fp32 accumulation; scores are float */
+    GS_BF16 = 1, /* bf16 weights (round to nearest even), fp32 accumulation, then
+                    fp64 rescoring of every candidate within the bf16 error band of
+                    the k-th score from the fp32 forward rows; scores are double and
+                    equal the fp64 sum over shared terms in ascending term order */
+    GS_U8 = 2    /* uint8 impacts q8(w) = round(w*255/3) (ties to even, saturated
+                    at 255) for document and query weights, exact int32
+                    accumulation; scores are int32 */
+};
+
+enum gs_build_flags {
+    GS_KEEP_FORWARD = 1 /* keep the fp32 doc-major rows on the device (needed by the
+                           document-parallel kernel; always kept for GS_BF16) */
+};
+
+/* Scoring kernels (Sec. 5.2 term-parallel scatter-add; Sec. 5.3 document-parallel). */
+enum gs_kernel {
+    GS_KERNEL_AUTO = 0,   /* library choice */
+    GS_KERNEL_TILED = 1,  /* term-parallel, per (query, doc tile): posting segments
+                             scatter-added into an LDS tile, one coalesced write per doc */
+    GS_KERNEL_ATOMIC = 2, /* term-parallel, per (query, term, posting chunk): global
+                             atomics into the score array (the paper's Sec. 5.2 form) */
+    GS_KERNEL_DOCPAR = 3, /* document-parallel: per (query, doc) gather over the
+                             forward rows, no atomics (Sec. 5.3); needs GS_KEEP_FORWARD */
+    GS_KERNEL_SHARED = 4  /* batched: per (query group, doc tile), each posting segment
+                             is read once and applied to every query of the group
+                             that holds its term */
+};
+
+#define GS_MAX_K 4096        /* largest k per query */
+#define GS_MAX_QUERY_NNZ 256  /* largest number of terms in one query */
+
+typedef struct gs_search_opts {
+    int32_t kernel;      /* gs_kernel */
+    int32_t query_tile;  /* most queries whose score arrays are live at once
+                            (0 = as many as the workspace holds) */
+    int32_t tile_docs;   /* doc tile of the TILED/SHARED kernels: 0 (default),
+                            8192, 16384 or 32768 */
+    int32_t chunk;       /* postings per work item (TILED/ATOMIC): 0 (default),
+                            64, 128, 256, 512 or 1024 */
+    int32_t group;       /* queries per workgroup (SHARED): 0 (default) or 1..8 */
+    int32_t reserved[3]; /* must be 0 */
+} gs_search_opts;
+
+typedef struct gs_index_info_t {
+    int64_t n_docs;
+    int64_t nnz;          /* real postings */
+    int64_t padded_nnz;   /* postings after padding each list to a multiple of 64 */
+    int64_t device_bytes; /* device memory held by the index */
+    int32_t vocab_size;
+    int32_t precision;    /* gs_precision */
+    uint32_t flags;       /* gs_build_flags in effect */
+    int32_t tile_grain;   /* doc-tile granularity of the segment table (docs) */
+    int64_t n_tiles;      /* tiles of tile_grain docs covering the collection */
+} gs_index_info_t;
+
+/* ------------------------------------------------------------------ misc -- */
+
+const char* gs_version(void);
+const char* gs_status_string(int32_t status);
+/* Message of the last failing call on this thread ("" if none). */
+const char* gs_last_error(void);
+
+/* ------------------------------------------------------------ index build -- */
+
+/*
+ * Build the GPU-resident inverted index (paper Sec. 3.2) from a doc-major CSR.
+ *
+ * row_ptr [n_docs+1] (host, int64): row_ptr[0] = 0, non-decreasing, row_ptr[n_docs] = nnz.
+ * term_ids [nnz] (host, int32): term of each entry, in [0, vocab_size); no term
+ *     twice in one row; rows need not be sorted.
+ * weights [nnz] (host, float): finite and >= 0 (learned sparse weights are
+ *     non-negative, Sec. 2.1).
+ * precision: gs_precision. flags: gs_build_flags.
+ *
+ * Layout built (all device-resident, owned by the index):
+ *  - posting lists term-major, each sorted by doc id (Sec. 3.2), padded with
+ *    (doc -1, weight 0) entries to a multiple of 64 (one wavefront);
+ *  - term_off[V+1] (int64) list starts, term_len[V] real lengths;
+ *  - per 64-posting block: the largest weight and the first doc id;
+ *  - per term and per tile of tile_grain docs: the offset of the first
+ *    posting at or after the tile start (segment table for doc-tiled kernels).
+ * Synchronous: returns once the index is on the device.
+ * Errors: GS_EINVAL (any check above, vocab_size < 1, n_docs < 0,
+ *   n_docs >= 2^31, unknown precision or flag), GS_ENOMEM, GS_EHIP.
+ */
+int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* term_ids,
+                       const float* weights, int64_t nnz, int32_t vocab_size, int32_t precision,
+                       uint32_t flags, void* hip_stream, gs_index* out);
+
+int32_t gs_index_info(gs_index index, gs_index_info_t* out);
+void gs_free_index(gs_index index);
+
+/*
+ * Host-only form of the posting layout gs_build_index puts on the device
+ * (same code path), for inspection and tests. Call first with
+ * out_padded_nnz != NULL and every array NULL to get the sizes, then again
+ * with caller-allocated arrays:
+ *   term_off [vocab_size+1] int64, term_len [vocab_size] int32,
+ *   post_doc [padded_nnz] int32, post_w [padded_nnz] float (the stored weight
+ *   converted back to float: fp32 as is, bf16 widened, uint8 as its integer),
+ *   blk_max [padded_nnz/64] float, blk_first_doc [padded_nnz/64] int32.
+ * Errors as gs_build_index.
+ */
+int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* term_ids,
+                       const float* weights, int64_t nnz, int32_t vocab_size, int32_t precision,
+                       int64_t* out_padded_nnz, int64_t* term_off, int32_t* term_len,
+                       int32_t* post_doc, float* post_w, float* blk_max, int32_t* blk_first_doc);
+
+/* --------------------------------------------------------- query batches -- */
+
+/*
+ * Validate a CSR batch of queries and copy it to the device (owned by the batch).
+ * q_row_ptr [n_queries+1] (host, int64), q_term_ids / q_weights [q_nnz] (host),
+ * k [n_queries] (host, int32) with 0 <= k[q] <= k_max <= GS_MAX_K.
+ * Query rows follow the same rules as document rows (terms in range, no
+ * duplicates, finite non-negative weights, at most GS_MAX_QUERY_NNZ terms).
+ * Synchronous. Errors: GS_EINVAL, GS_ENOMEM, GS_EHIP.
+ */
+int32_t gs_batch_create(gs_index index, const int64_t* q_row_ptr, int32_t n_queries,
+                        const int32_t* q_term_ids, const float* q_weights, int64_t q_nnz,
+                        const int32_t* k, int32_t k_max, void* hip_stream, gs_batch* out);
+void gs_batch_free(gs_batch batch);
+
+/*
+ * Device workspace (bytes) needed to search query_tile queries at once with
+ * these options (opts may be NULL). It holds one score array of n_docs 32-bit
+ * words per live query plus selection scratch.
+ */
+int32_t gs_workspace_size(gs_index index, int32_t query_tile, const gs_search_opts* opts,
+                          size_t* bytes);
+
+/*
+ * Search a prepared batch: exact top-k per query.
+ * workspace: device, workspace_bytes >= gs_workspace_size(index, 1, opts);
+ *   queries are processed in tiles of as many as the workspace holds
+ *   (score arrays tiled to fit memory).
+ * out_ids [n_queries * k_max] (device, int32).
+ * out_scores [n_queries * k_max] (device): float for GS_FP32, double for
+ *   GS_BF16, int32 for GS_U8.
+ * Asynchronous on hip_stream. The index and batch are only read, so searches
+ * with separate workspaces and outputs may run concurrently on different streams.
+ * Errors: GS_EINVAL (NULL arguments, bad opts), GS_ECAPACITY (workspace too
+ *   small), GS_EUNSUPPORTED (kernel not available for this index), GS_EHIP.
+ */
+int32_t gs_search_batch(gs_index index, gs_batch batch, void* workspace, size_t workspace_bytes,
+                        int32_t* out_ids, void* out_scores, const gs_search_opts* opts,
+                        void* hip_stream);
+
+/*
+ * Convenience form: gs_batch_create + gs_search_batch + gs_batch_free.
+ * Synchronous (the stream is synchronised before returning).
+ */
+int32_t gs_search(gs_index index, const int64_t* q_row_ptr, int32_t n_queries,
+                  const int32_t* q_term_ids, const float* q_weights, int64_t q_nnz,
+                  const int32_t* k, int32_t k_max, void* workspace, size_t workspace_bytes,
+                  int32_t* out_ids, void* out_scores, const gs_search_opts* opts,
+                  void* hip_stream);
+
+/*
+ * Per-query selection diagnostics of the last gs_search_batch on this batch
+ * (host copy; call after the stream has been synchronised).
+ * out [n_queries * 4] int32: candidates kept by the filter, refinement passes
+ * over the score array, bf16 band size (0 for other precisions), and an
+ * overflow flag (1 if the candidate buffer overflowed; the row is then
+ * invalid and the search call must be repeated with a larger workspace).
+ */
+int32_t gs_batch_diagnostics(gs_batch batch, int32_t* out);
+
+/*
+ * Kernel timing for measurement. While enabled (on != 0), gs_search_batch
+ * records a HIP event pair on its stream around every scoring launch and
+ * around every selection (top-k) sequence. gs_timing_read synchronises those
+ * events, returns the summed milliseconds and launch counts since the
+ * previous read (any output pointer may be NULL) and releases the events.
+ * Process-wide; thread-safe. Errors: GS_EHIP.
+ */
+int32_t gs_timing_enable(int32_t on);
+int32_t gs_timing_read(double* score_ms, int64_t* score_launches, double* select_ms,
+                       int64_t* select_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPUSPARSE_H */

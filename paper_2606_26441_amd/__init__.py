@@ -1,0 +1,275 @@
+"""Python binding of libgpusparse.so: exact learned-sparse retrieval on MI355X.
+
+Argument marshalling only. Every step of index build and search runs in the
+C++/HIP library behind ``include/gpusparse.h``; PyTorch provides device memory
+(workspace and output tensors) and the HIP stream. Importing this module fails
+when the library has not been built (``python paper_2606_26441_amd/build.py``):
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+import torch  # loads the HIP runtime that the library then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpusparse.so")
+
+GS_OK, GS_EINVAL, GS_ENOMEM, GS_EHIP, GS_ECAPACITY, GS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GS_FP32, GS_BF16, GS_U8 = 0, 1, 2
+GS_KEEP_FORWARD = 1
+GS_KERNEL_AUTO, GS_KERNEL_TILED, GS_KERNEL_ATOMIC, GS_KERNEL_DOCPAR, GS_KERNEL_SHARED = 0, 1, 2, 3, 4
+GS_MAX_K = 4096
+GS_MAX_QUERY_NNZ = 256
+
+PRECISIONS = {"fp32": GS_FP32, "bf16": GS_BF16, "u8": GS_U8}
+KERNELS = {"auto": GS_KERNEL_AUTO, "tiled": GS_KERNEL_TILED, "atomic": GS_KERNEL_ATOMIC,
+           "docpar": GS_KERNEL_DOCPAR, "shared": GS_KERNEL_SHARED}
+SCORE_DTYPES = {GS_FP32: torch.float32, GS_BF16: torch.float64, GS_U8: torch.int32}
+
+
+class GsError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__("%s failed: %s (%d): %s" % (where, _STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+_STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error", -4: "capacity exceeded",
+           -5: "unsupported"}
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("query_tile", ctypes.c_int32), ("tile_docs", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("group", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("n_docs", ctypes.c_int64), ("nnz", ctypes.c_int64), ("padded_nnz", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("vocab_size", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("tile_grain", ctypes.c_int32), ("n_tiles", ctypes.c_int64)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgpusparse.so is not built (run: python paper_2606_26441_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, u32, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
+    P = ctypes.POINTER
+    lib.gs_version.restype = ctypes.c_char_p
+    lib.gs_status_string.argtypes = [i32]
+    lib.gs_status_string.restype = ctypes.c_char_p
+    lib.gs_last_error.restype = ctypes.c_char_p
+    lib.gs_build_index.argtypes = [vp, i64, vp, vp, i64, i32, i32, u32, vp, P(vp)]
+    lib.gs_build_index.restype = i32
+    lib.gs_index_info.argtypes = [vp, P(IndexInfo)]
+    lib.gs_index_info.restype = i32
+    lib.gs_free_index.argtypes = [vp]
+    lib.gs_free_index.restype = None
+    lib.gs_layout_host.argtypes = [vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.gs_layout_host.restype = i32
+    lib.gs_batch_create.argtypes = [vp, vp, i32, vp, vp, i64, vp, i32, vp, P(vp)]
+    lib.gs_batch_create.restype = i32
+    lib.gs_batch_free.argtypes = [vp]
+    lib.gs_batch_free.restype = None
+    lib.gs_workspace_size.argtypes = [vp, i32, P(SearchOpts), P(sz)]
+    lib.gs_workspace_size.restype = i32
+    lib.gs_search_batch.argtypes = [vp, vp, vp, sz, vp, vp, P(SearchOpts), vp]
+    lib.gs_search_batch.restype = i32
+    lib.gs_search.argtypes = [vp, vp, i32, vp, vp, i64, vp, i32, vp, sz, vp, vp, P(SearchOpts), vp]
+    lib.gs_search.restype = i32
+    lib.gs_batch_diagnostics.argtypes = [vp, vp]
+    lib.gs_batch_diagnostics.restype = i32
+    lib.gs_timing_enable.argtypes = [i32]
+    lib.gs_timing_enable.restype = i32
+    lib.gs_timing_read.argtypes = [P(ctypes.c_double), P(i64), P(ctypes.c_double), P(i64)]
+    lib.gs_timing_read.restype = i32
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int, where: str):
+    if rc != GS_OK:
+        raise GsError(rc, where, lib.gs_last_error().decode())
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _stream_ptr(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def make_opts(kernel="auto", query_tile=0, tile_docs=0, chunk=0, group=0) -> SearchOpts:
+    o = SearchOpts()
+    o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    o.query_tile, o.tile_docs, o.chunk, o.group = int(query_tile), int(tile_docs), int(chunk), int(group)
+    return o
+
+
+def layout_host(row_ptr, terms, weights, vocab: int, precision="fp32"):
+    """Host-only posting layout (same code as the device index build), as numpy arrays."""
+    rp, t, w = _np(row_ptr, np.int64), _np(terms, np.int32), _np(weights, np.float32)
+    n = rp.shape[0] - 1
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    padded = ctypes.c_int64(0)
+    _check(lib.gs_layout_host(rp.ctypes.data, n, t.ctypes.data, w.ctypes.data, t.shape[0], vocab, prec,
+                              ctypes.addressof(padded), None, None, None, None, None, None), "gs_layout_host")
+    P = padded.value
+    out = dict(term_off=np.empty(vocab + 1, np.int64), term_len=np.empty(vocab, np.int32),
+               post_doc=np.empty(P, np.int32), post_w=np.empty(P, np.float32),
+               blk_max=np.empty(P // 64, np.float32), blk_first_doc=np.empty(P // 64, np.int32))
+    _check(lib.gs_layout_host(rp.ctypes.data, n, t.ctypes.data, w.ctypes.data, t.shape[0], vocab, prec,
+                              ctypes.addressof(padded), out["term_off"].ctypes.data, out["term_len"].ctypes.data,
+                              out["post_doc"].ctypes.data, out["post_w"].ctypes.data, out["blk_max"].ctypes.data,
+                              out["blk_first_doc"].ctypes.data), "gs_layout_host")
+    return out
+
+
+class Index:
+    """GPU-resident inverted index built from a doc-major CSR (row_ptr, terms, weights)."""
+
+    def __init__(self, row_ptr, terms, weights, vocab: int, precision="fp32", keep_forward: bool = False,
+                 stream=None):
+        rp, t, w = _np(row_ptr, np.int64), _np(terms, np.int32), _np(weights, np.float32)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        flags = GS_KEEP_FORWARD if keep_forward else 0
+        h = ctypes.c_void_p()
+        _check(lib.gs_build_index(rp.ctypes.data, rp.shape[0] - 1, t.ctypes.data, w.ctypes.data, t.shape[0], vocab,
+                                  self.precision, flags, _stream_ptr(stream), ctypes.byref(h)), "gs_build_index")
+        self._h = h
+        self.vocab = vocab
+
+    @classmethod
+    def from_rows(cls, rows, precision="fp32", keep_forward=False, stream=None):
+        return cls(rows.row_ptr, rows.terms, rows.weights, rows.vocab, precision, keep_forward, stream)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> IndexInfo:
+        i = IndexInfo()
+        _check(lib.gs_index_info(self._h, ctypes.byref(i)), "gs_index_info")
+        return i
+
+    @property
+    def n_docs(self) -> int:
+        return int(self.info().n_docs)
+
+    def workspace_bytes(self, query_tile: int, opts: Optional[SearchOpts] = None) -> int:
+        n = ctypes.c_size_t(0)
+        _check(lib.gs_workspace_size(self._h, int(query_tile), ctypes.byref(opts) if opts else None,
+                                     ctypes.byref(n)), "gs_workspace_size")
+        return int(n.value)
+
+    def workspace(self, query_tile: int, opts: Optional[SearchOpts] = None, device="cuda") -> torch.Tensor:
+        return torch.empty(self.workspace_bytes(query_tile, opts), dtype=torch.uint8, device=device)
+
+    def batch(self, queries, k, k_max: Optional[int] = None, stream=None) -> "Batch":
+        return Batch(self, queries.row_ptr, queries.terms, queries.weights, k, k_max, stream)
+
+    def search(self, batch: "Batch", workspace: Optional[torch.Tensor] = None, opts: Optional[SearchOpts] = None,
+               out=None, stream=None):
+        """Exact top-k of a prepared batch. Returns (ids [n, k_max] int32, scores [n, k_max]) on the device."""
+        if workspace is None:
+            workspace = self.workspace(max(1, min(batch.n_queries, 64)), opts)
+        if out is None:
+            ids = torch.empty((batch.n_queries, batch.k_max), dtype=torch.int32, device=workspace.device)
+            scores = torch.empty((batch.n_queries, batch.k_max), dtype=SCORE_DTYPES[self.precision],
+                                 device=workspace.device)
+        else:
+            ids, scores = out
+        _check(lib.gs_search_batch(self._h, batch.handle, workspace.data_ptr(), workspace.numel(), ids.data_ptr(),
+                                   scores.data_ptr(), ctypes.byref(opts) if opts else None, _stream_ptr(stream)),
+               "gs_search_batch")
+        return ids, scores
+
+    def search_host(self, queries, k, k_max: Optional[int] = None, workspace: Optional[torch.Tensor] = None,
+                    opts: Optional[SearchOpts] = None, stream=None):
+        """gs_search: host CSR in, synchronous."""
+        rp, t, w = _np(queries.row_ptr, np.int64), _np(queries.terms, np.int32), _np(queries.weights, np.float32)
+        nq = rp.shape[0] - 1
+        kk = np.broadcast_to(np.asarray(k, dtype=np.int32), (nq,)).copy()
+        k_max = int(kk.max()) if k_max is None and nq else int(k_max or 0)
+        if workspace is None:
+            workspace = self.workspace(max(1, min(nq, 64)), opts)
+        ids = torch.empty((nq, k_max), dtype=torch.int32, device=workspace.device)
+        scores = torch.empty((nq, k_max), dtype=SCORE_DTYPES[self.precision], device=workspace.device)
+        _check(lib.gs_search(self._h, rp.ctypes.data, nq, t.ctypes.data, w.ctypes.data, t.shape[0], kk.ctypes.data,
+                             k_max, workspace.data_ptr(), workspace.numel(), ids.data_ptr(), scores.data_ptr(),
+                             ctypes.byref(opts) if opts else None, _stream_ptr(stream)), "gs_search")
+        return ids, scores
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.gs_free_index(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A validated query batch resident on the device."""
+
+    def __init__(self, index: Index, row_ptr, terms, weights, k, k_max=None, stream=None):
+        rp, t, w = _np(row_ptr, np.int64), _np(terms, np.int32), _np(weights, np.float32)
+        nq = rp.shape[0] - 1
+        kk = np.broadcast_to(np.asarray(k, dtype=np.int32), (nq,)).copy()
+        self.k = kk
+        self.k_max = int(kk.max()) if k_max is None and nq else int(k_max or 0)
+        self.n_queries = nq
+        h = ctypes.c_void_p()
+        _check(lib.gs_batch_create(index.handle, rp.ctypes.data, nq, t.ctypes.data, w.ctypes.data, t.shape[0],
+                                   kk.ctypes.data, self.k_max, _stream_ptr(stream), ctypes.byref(h)),
+               "gs_batch_create")
+        self._h = h
+        self._index = index
+
+    @property
+    def handle(self):
+        return self._h
+
+    def diagnostics(self) -> np.ndarray:
+        """[n_queries, 4]: candidates, refinement passes, bf16 band size, overflow flag."""
+        out = np.zeros((self.n_queries, 4), dtype=np.int32)
+        _check(lib.gs_batch_diagnostics(self._h, out.ctypes.data), "gs_batch_diagnostics")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.gs_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def version() -> str:
+    return lib.gs_version().decode()
+
+
+def timing_enable(on: bool = True):
+    _check(lib.gs_timing_enable(1 if on else 0), "gs_timing_enable")
+
+
+def timing_read():
+    """{'score_ms', 'score_launches', 'select_ms', 'select_launches'} summed since the previous read."""
+    a, c = ctypes.c_double(0), ctypes.c_double(0)
+    b, d = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib.gs_timing_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)), "gs_timing_read")
+    return {"score_ms": a.value, "score_launches": b.value, "select_ms": c.value, "select_launches": d.value}

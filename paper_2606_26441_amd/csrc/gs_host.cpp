@@ -1,0 +1,810 @@
+// Host side of libgpusparse.so: argument validation, the term-major posting
+// layout (paper Sec. 3.2), device residency of the index and of query
+// batches, workspace carving and the per-tile launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/gpusparse.h"
+#include "gs_internal.h"
+
+using namespace gs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define GS_HIP(call)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? GS_ENOMEM : GS_EHIP,                              \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                           \
+    } while (0)
+
+int n_workers() {
+    unsigned h = std::thread::hardware_concurrency();
+    if (h == 0) h = 4;
+    return (int)std::min(h, 16u);
+}
+
+template <typename F>
+void parallel_for(int64_t n, F f) {
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(n_workers(), n / 4096 + 1));
+    if (T == 1) {
+        f(0, (int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 0; t < T; t++) {
+        const int64_t a = n * t / T, b = n * (t + 1) / T;
+        th.emplace_back([=, &f] { f(t, a, b); });
+    }
+    for (auto& x : th) x.join();
+}
+
+inline uint16_t bf16_rne(float w) {
+    uint32_t u;
+    std::memcpy(&u, &w, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+inline float bf16_widen(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// uint8 impact: round(w * 255 / 3) with ties to even, saturated to [0, 255].
+inline uint8_t q8(float w) {
+    const double x = std::nearbyint((double)w * 85.0);
+    return x > 255.0 ? 255 : (x > 0.0 ? (uint8_t)x : 0);
+}
+
+// ----------------------------------------------------------- CSR checks --
+
+struct Rows {
+    const int64_t* row_ptr;
+    const int32_t* term;
+    const float* w;
+    int64_t n;
+    std::vector<int32_t> term_sorted;  // filled when some input row is unsorted
+    std::vector<float> w_sorted;
+};
+
+// Validate a CSR of (term, weight) rows; when a row is unsorted, keep a sorted copy.
+int32_t check_rows(Rows& r, int64_t nnz, int32_t vocab, int64_t max_row, const char* what) {
+    if (r.n < 0 || nnz < 0) return fail(GS_EINVAL, std::string(what) + ": negative size");
+    if (r.n > 0 || nnz > 0) {
+        if (!r.row_ptr) return fail(GS_EINVAL, std::string(what) + ": null row_ptr");
+        if (nnz > 0 && (!r.term || !r.w)) return fail(GS_EINVAL, std::string(what) + ": null arrays");
+    }
+    if (r.row_ptr && r.row_ptr[0] != 0) return fail(GS_EINVAL, std::string(what) + ": row_ptr[0] != 0");
+    if (r.row_ptr && r.row_ptr[r.n] != nnz) return fail(GS_EINVAL, std::string(what) + ": row_ptr[n] != nnz");
+    for (int64_t i = 0; i < r.n; i++)
+        if (r.row_ptr[i + 1] < r.row_ptr[i] || r.row_ptr[i + 1] - r.row_ptr[i] > max_row)
+            return fail(GS_EINVAL, std::string(what) + ": row " + std::to_string(i) +
+                                       " has a negative length or more than " + std::to_string(max_row) + " terms");
+    std::atomic<int> bad{0}, unsorted{0};
+    parallel_for(r.n, [&](int, int64_t a, int64_t b) {
+        for (int64_t i = a; i < b && !bad.load(std::memory_order_relaxed); i++) {
+            for (int64_t j = r.row_ptr[i]; j < r.row_ptr[i + 1]; j++) {
+                const float w = r.w[j];
+                if (r.term[j] < 0 || r.term[j] >= vocab) { bad = 1; break; }
+                if (!std::isfinite(w) || w < 0.0f) { bad = 2; break; }
+                if (j > r.row_ptr[i] && r.term[j] <= r.term[j - 1]) {
+                    if (r.term[j] == r.term[j - 1]) { bad = 3; break; }
+                    unsorted = 1;
+                }
+            }
+        }
+    });
+    if (bad == 1) return fail(GS_EINVAL, std::string(what) + ": term id out of range");
+    if (bad == 2) return fail(GS_EINVAL, std::string(what) + ": weight negative or not finite");
+    if (bad == 3) return fail(GS_EINVAL, std::string(what) + ": duplicate term in a row");
+    if (unsorted) {
+        r.term_sorted.resize((size_t)nnz);
+        r.w_sorted.resize((size_t)nnz);
+        parallel_for(r.n, [&](int, int64_t a, int64_t b) {
+            std::vector<std::pair<int32_t, float>> tmp;
+            for (int64_t i = a; i < b; i++) {
+                const int64_t s = r.row_ptr[i], e = r.row_ptr[i + 1];
+                tmp.clear();
+                for (int64_t j = s; j < e; j++) tmp.emplace_back(r.term[j], r.w[j]);
+                std::sort(tmp.begin(), tmp.end(),
+                          [](const std::pair<int32_t, float>& x, const std::pair<int32_t, float>& y) {
+                              return x.first < y.first;
+                          });
+                for (int64_t j = s; j < e; j++) {
+                    r.term_sorted[(size_t)j] = tmp[(size_t)(j - s)].first;
+                    r.w_sorted[(size_t)j] = tmp[(size_t)(j - s)].second;
+                    if (j > s && tmp[(size_t)(j - s)].first == tmp[(size_t)(j - s - 1)].first) bad = 3;
+                }
+            }
+        });
+        if (bad == 3) return fail(GS_EINVAL, std::string(what) + ": duplicate term in a row");
+        r.term = r.term_sorted.data();
+        r.w = r.w_sorted.data();
+    }
+    return GS_OK;
+}
+
+// ------------------------------------------------------- posting layout --
+
+struct Layout {
+    int64_t n_docs = 0, nnz = 0, padded = 0, n_grains = 0;
+    int32_t vocab = 0, precision = 0;
+    std::vector<int64_t> term_off;   // [V+1]
+    std::vector<int32_t> term_len;   // [V]
+    std::vector<int32_t> post_doc;   // [padded]
+    std::vector<float> w_f32;        // [padded] (GS_FP32)
+    std::vector<uint16_t> w_bf16;    // [padded] (GS_BF16)
+    std::vector<uint8_t> w_u8;       // [padded] (GS_U8)
+    std::vector<float> blk_max;      // [padded / 64]
+    std::vector<int32_t> blk_first;  // [padded / 64]
+    std::vector<int32_t> tile_off;   // [V][n_grains+1]
+};
+
+float stored_weight(const Layout& L, int64_t i) {
+    switch (L.precision) {
+        case kFP32: return L.w_f32[(size_t)i];
+        case kBF16: return bf16_widen(L.w_bf16[(size_t)i]);
+        default: return (float)L.w_u8[(size_t)i];
+    }
+}
+
+int32_t sizes_only(const Rows& r, int32_t vocab, Layout& L) {
+    std::vector<int64_t> df((size_t)vocab, 0);
+    for (int64_t j = 0; j < r.row_ptr[r.n]; j++) df[(size_t)r.term[j]]++;
+    L.padded = 0;
+    for (int32_t t = 0; t < vocab; t++) L.padded += (df[(size_t)t] + kBlock - 1) / kBlock * kBlock;
+    return GS_OK;
+}
+
+int32_t build_layout(const Rows& r, int32_t vocab, int32_t precision, bool tiles, Layout& L) {
+    const int64_t N = r.n, nnz = r.n > 0 ? r.row_ptr[r.n] : 0;
+    L.n_docs = N;
+    L.nnz = nnz;
+    L.vocab = vocab;
+    L.precision = precision;
+    try {
+        // term counts per worker over contiguous doc ranges (docs stay in order per term)
+        const int T = std::max<int64_t>(1, std::min<int64_t>(n_workers(), N / 4096 + 1));
+        std::vector<std::vector<int64_t>> cnt((size_t)T, std::vector<int64_t>((size_t)vocab, 0));
+        std::vector<int64_t> lo((size_t)T + 1);
+        for (int t = 0; t <= T; t++) lo[(size_t)t] = N * t / T;
+        {
+            std::vector<std::thread> th;
+            for (int t = 0; t < T; t++)
+                th.emplace_back([&, t] {
+                    auto& c = cnt[(size_t)t];
+                    for (int64_t j = r.row_ptr[lo[(size_t)t]]; j < r.row_ptr[lo[(size_t)t + 1]]; j++)
+                        c[(size_t)r.term[j]]++;
+                });
+            for (auto& x : th) x.join();
+        }
+        L.term_off.assign((size_t)vocab + 1, 0);
+        L.term_len.assign((size_t)vocab, 0);
+        for (int32_t v = 0; v < vocab; v++) {
+            int64_t df = 0;
+            for (int t = 0; t < T; t++) df += cnt[(size_t)t][(size_t)v];
+            L.term_len[(size_t)v] = (int32_t)df;
+            L.term_off[(size_t)v + 1] = L.term_off[(size_t)v] + (df + kBlock - 1) / kBlock * kBlock;
+        }
+        L.padded = L.term_off[(size_t)vocab];
+        // per-worker write cursors
+        for (int32_t v = 0; v < vocab; v++) {
+            int64_t run = L.term_off[(size_t)v];
+            for (int t = 0; t < T; t++) {
+                const int64_t c = cnt[(size_t)t][(size_t)v];
+                cnt[(size_t)t][(size_t)v] = run;
+                run += c;
+            }
+        }
+        L.post_doc.assign((size_t)L.padded, -1);
+        if (precision == kFP32) L.w_f32.assign((size_t)L.padded, 0.0f);
+        if (precision == kBF16) L.w_bf16.assign((size_t)L.padded, 0);
+        if (precision == kU8) L.w_u8.assign((size_t)L.padded, 0);
+        {
+            std::vector<std::thread> th;
+            for (int t = 0; t < T; t++)
+                th.emplace_back([&, t] {
+                    auto& cur = cnt[(size_t)t];
+                    for (int64_t d = lo[(size_t)t]; d < lo[(size_t)t + 1]; d++) {
+                        for (int64_t j = r.row_ptr[d]; j < r.row_ptr[d + 1]; j++) {
+                            const int64_t p = cur[(size_t)r.term[j]]++;
+                            L.post_doc[(size_t)p] = (int32_t)d;
+                            if (precision == kFP32) L.w_f32[(size_t)p] = r.w[j];
+                            else if (precision == kBF16) L.w_bf16[(size_t)p] = bf16_rne(r.w[j]);
+                            else L.w_u8[(size_t)p] = q8(r.w[j]);
+                        }
+                    }
+                });
+            for (auto& x : th) x.join();
+        }
+        // block-max metadata per 64-posting block
+        const int64_t nb = L.padded / kBlock;
+        L.blk_max.assign((size_t)nb, 0.0f);
+        L.blk_first.assign((size_t)nb, -1);
+        parallel_for(nb, [&](int, int64_t a, int64_t b) {
+            for (int64_t k = a; k < b; k++) {
+                float m = 0.0f;
+                for (int64_t i = k * kBlock; i < (k + 1) * kBlock; i++) m = std::max(m, stored_weight(L, i));
+                L.blk_max[(size_t)k] = m;
+                L.blk_first[(size_t)k] = L.post_doc[(size_t)(k * kBlock)];
+            }
+        });
+        // segment table: first posting at or after each 8192-doc grain start
+        L.n_grains = (N + (1 << kGrainShift) - 1) >> kGrainShift;
+        if (tiles) {
+            const int64_t G = L.n_grains + 1;
+            L.tile_off.assign((size_t)vocab * (size_t)G, 0);
+            parallel_for(vocab, [&](int, int64_t a, int64_t b) {
+                for (int64_t v = a; v < b; v++) {
+                    const int32_t* docs = L.post_doc.data() + L.term_off[(size_t)v];
+                    const int32_t len = L.term_len[(size_t)v];
+                    int32_t* row = L.tile_off.data() + v * G;
+                    int32_t i = 0;
+                    for (int64_t g = 0; g < G; g++) {
+                        const int64_t start = g << kGrainShift;
+                        while (i < len && docs[i] < start) i++;
+                        row[g] = i;
+                    }
+                }
+            });
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(GS_ENOMEM, "host allocation failed while building the posting layout");
+    }
+    return GS_OK;
+}
+
+}  // namespace
+
+// ===================================================================== API ==
+
+struct gs_index_s {
+    int device = 0;
+    int64_t n_docs = 0, nnz = 0, padded = 0, n_grains = 0;
+    int32_t vocab = 0, precision = 0;
+    uint32_t flags = 0;
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+    DevIndex dev{};
+    ~gs_index_s() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+};
+
+struct gs_batch_s {
+    gs_index index = nullptr;
+    int32_t n_queries = 0, k_max = 0;
+    int64_t q_nnz = 0;
+    std::vector<void*> allocs;
+    DevBatch dev{};
+    int32_t* diag = nullptr;  // [n_queries * 4]
+    ~gs_batch_s() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+template <typename T>
+int32_t dev_upload(std::vector<void*>& allocs, size_t& bytes, const T* host, size_t n, T** out, hipStream_t s) {
+    *out = nullptr;
+    if (n == 0) n = 1;  // keep a valid pointer for empty arrays
+    void* p = nullptr;
+    GS_HIP(hipMalloc(&p, n * sizeof(T)));
+    allocs.push_back(p);
+    bytes += n * sizeof(T);
+    if (host) GS_HIP(hipMemcpyAsync(p, host, n * sizeof(T), hipMemcpyHostToDevice, s));
+    *out = (T*)p;
+    return GS_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// ---- kernel timing (measurement only) ----
+struct TimedSpan {
+    hipEvent_t a, b;
+    int kind;  // 0 scoring, 1 selection
+};
+std::mutex g_timing_mu;
+bool g_timing_on = false;
+std::vector<TimedSpan> g_spans;
+
+bool timing_on() {
+    std::lock_guard<std::mutex> l(g_timing_mu);
+    return g_timing_on;
+}
+
+struct SpanRecorder {
+    TimedSpan span{};
+    bool active = false;
+    SpanRecorder(int kind, hipStream_t s) {
+        if (!timing_on()) return;
+        span.kind = kind;
+        if (hipEventCreate(&span.a) != hipSuccess) return;
+        if (hipEventCreate(&span.b) != hipSuccess) {
+            (void)hipEventDestroy(span.a);
+            return;
+        }
+        active = hipEventRecord(span.a, s) == hipSuccess;
+    }
+    void end(hipStream_t s) {
+        if (!active) return;
+        if (hipEventRecord(span.b, s) == hipSuccess) {
+            std::lock_guard<std::mutex> l(g_timing_mu);
+            g_spans.push_back(span);
+        } else {
+            (void)hipEventDestroy(span.a);
+            (void)hipEventDestroy(span.b);
+        }
+        active = false;
+    }
+};
+
+}  // namespace
+
+namespace gs {
+
+size_t workspace_bytes(int64_t n_docs, int32_t qt, int32_t precision) {
+    const size_t ld = (size_t)((n_docs + 63) / 64 * 64);
+    size_t b = 0;
+    b += align256((size_t)qt * ld * 4);
+    b += 2 * align256((size_t)qt * kHistBins * 4);
+    b += align256((size_t)qt * sizeof(SelState));
+    b += align256((size_t)qt * kCandCap * 8);
+    if (precision == kBF16) {
+        b += align256((size_t)qt * kCandCap * 8);
+        b += align256((size_t)qt * kCandCap * 4);
+    }
+    b += align256(((size_t)qt * kMaxQueryNnz + 1) * 8);
+    b += align256((size_t)qt * kMaxQueryNnz * 4);
+    return b;
+}
+
+void carve_workspace(void* base, int64_t n_docs, int32_t qt, int32_t precision, Workspace* ws) {
+    const size_t ld = (size_t)((n_docs + 63) / 64 * 64);
+    char* p = (char*)base;
+    auto take = [&](size_t n) {
+        char* r = p;
+        p += align256(n);
+        return r;
+    };
+    ws->ld = (int64_t)ld;
+    ws->scores = (uint32_t*)take((size_t)qt * ld * 4);
+    ws->hist1 = (uint32_t*)take((size_t)qt * kHistBins * 4);
+    ws->hist_ref = (uint32_t*)take((size_t)qt * kHistBins * 4);
+    ws->state = (SelState*)take((size_t)qt * sizeof(SelState));
+    ws->cand = (unsigned long long*)take((size_t)qt * kCandCap * 8);
+    ws->band_s = nullptr;
+    ws->band_id = nullptr;
+    if (precision == kBF16) {
+        ws->band_s = (double*)take((size_t)qt * kCandCap * 8);
+        ws->band_id = (int32_t*)take((size_t)qt * kCandCap * 4);
+    }
+    ws->work_prefix = (int64_t*)take(((size_t)qt * kMaxQueryNnz + 1) * 8);
+    ws->work_pair_q = (int32_t*)take((size_t)qt * kMaxQueryNnz * 4);
+}
+
+}  // namespace gs
+
+extern "C" {
+
+const char* gs_version(void) { return "gpusparse-mi355x 0.1 (gfx950)"; }
+
+const char* gs_status_string(int32_t s) {
+    switch (s) {
+        case GS_OK: return "ok";
+        case GS_EINVAL: return "invalid argument";
+        case GS_ENOMEM: return "out of memory";
+        case GS_EHIP: return "HIP runtime error";
+        case GS_ECAPACITY: return "capacity exceeded";
+        case GS_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* gs_last_error(void) { return g_err.c_str(); }
+
+int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* term_ids, const float* weights,
+                       int64_t nnz, int32_t vocab_size, int32_t precision, int64_t* out_padded_nnz, int64_t* term_off,
+                       int32_t* term_len, int32_t* post_doc, float* post_w, float* blk_max, int32_t* blk_first_doc) {
+    g_err.clear();
+    if (vocab_size < 1) return fail(GS_EINVAL, "vocab_size < 1");
+    if (precision < kFP32 || precision > kU8) return fail(GS_EINVAL, "unknown precision");
+    if (n_docs >= (int64_t)1 << 31) return fail(GS_EINVAL, "n_docs must be < 2^31");
+    Rows r{row_ptr, term_ids, weights, n_docs, {}, {}};
+    int32_t rc = check_rows(r, nnz, vocab_size, vocab_size, "documents");
+    if (rc != GS_OK) return rc;
+    Layout L;
+    const bool want_arrays = term_off || term_len || post_doc || post_w || blk_max || blk_first_doc;
+    if (!want_arrays) {
+        if (!out_padded_nnz) return fail(GS_EINVAL, "nothing requested");
+        sizes_only(r, vocab_size, L);
+        *out_padded_nnz = L.padded;
+        return GS_OK;
+    }
+    rc = build_layout(r, vocab_size, precision, false, L);
+    if (rc != GS_OK) return rc;
+    if (out_padded_nnz) *out_padded_nnz = L.padded;
+    if (term_off) std::memcpy(term_off, L.term_off.data(), L.term_off.size() * 8);
+    if (term_len) std::memcpy(term_len, L.term_len.data(), L.term_len.size() * 4);
+    if (post_doc) std::memcpy(post_doc, L.post_doc.data(), L.post_doc.size() * 4);
+    if (post_w)
+        for (int64_t i = 0; i < L.padded; i++) post_w[i] = stored_weight(L, i);
+    if (blk_max) std::memcpy(blk_max, L.blk_max.data(), L.blk_max.size() * 4);
+    if (blk_first_doc) std::memcpy(blk_first_doc, L.blk_first.data(), L.blk_first.size() * 4);
+    return GS_OK;
+}
+
+int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* term_ids, const float* weights,
+                       int64_t nnz, int32_t vocab_size, int32_t precision, uint32_t flags, void* hip_stream,
+                       gs_index* out) {
+    g_err.clear();
+    if (!out) return fail(GS_EINVAL, "out is null");
+    *out = nullptr;
+    if (vocab_size < 1) return fail(GS_EINVAL, "vocab_size < 1");
+    if (precision < kFP32 || precision > kU8) return fail(GS_EINVAL, "unknown precision");
+    if (flags & ~(uint32_t)GS_KEEP_FORWARD) return fail(GS_EINVAL, "unknown flag");
+    if (n_docs >= (int64_t)1 << 31) return fail(GS_EINVAL, "n_docs must be < 2^31");
+    Rows r{row_ptr, term_ids, weights, n_docs, {}, {}};
+    int32_t rc = check_rows(r, nnz, vocab_size, vocab_size, "documents");
+    if (rc != GS_OK) return rc;
+    Layout L;
+    rc = build_layout(r, vocab_size, precision, true, L);
+    if (rc != GS_OK) return rc;
+
+    hipStream_t s = (hipStream_t)hip_stream;
+    gs_index ix = new (std::nothrow) gs_index_s();
+    if (!ix) return fail(GS_ENOMEM, "host allocation failed");
+    (void)hipGetDevice(&ix->device);
+    ix->n_docs = n_docs;
+    ix->nnz = nnz;
+    ix->padded = L.padded;
+    ix->n_grains = L.n_grains;
+    ix->vocab = vocab_size;
+    ix->precision = precision;
+    if (precision == kBF16) flags |= GS_KEEP_FORWARD;
+    ix->flags = flags;
+    DevIndex& d = ix->dev;
+    d.n_docs = n_docs;
+    d.vocab = vocab_size;
+    d.precision = precision;
+    d.n_grains = L.n_grains;
+    auto done = [&](int32_t code) {
+        if (code != GS_OK) delete ix;
+        return code;
+    };
+    int64_t* term_off = nullptr;
+    int32_t *term_len = nullptr, *post_doc = nullptr, *tile_off = nullptr;
+    if ((rc = dev_upload(ix->allocs, ix->bytes, L.term_off.data(), L.term_off.size(), &term_off, s))) return done(rc);
+    if ((rc = dev_upload(ix->allocs, ix->bytes, L.term_len.data(), L.term_len.size(), &term_len, s))) return done(rc);
+    if ((rc = dev_upload(ix->allocs, ix->bytes, L.post_doc.data(), L.post_doc.size(), &post_doc, s))) return done(rc);
+    if ((rc = dev_upload(ix->allocs, ix->bytes, L.tile_off.data(), L.tile_off.size(), &tile_off, s))) return done(rc);
+    d.term_off = term_off;
+    d.term_len = term_len;
+    d.post_doc = post_doc;
+    d.tile_off = tile_off;
+    if (precision == kFP32) {
+        float* p = nullptr;
+        if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_f32.data(), L.w_f32.size(), &p, s))) return done(rc);
+        d.post_w = p;
+    } else if (precision == kBF16) {
+        uint16_t* p = nullptr;
+        if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_bf16.data(), L.w_bf16.size(), &p, s))) return done(rc);
+        d.post_w = p;
+    } else {
+        uint8_t* p = nullptr;
+        if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_u8.data(), L.w_u8.size(), &p, s))) return done(rc);
+        d.post_w = p;
+    }
+    float* blk_max = nullptr;
+    int32_t* blk_first = nullptr;
+    if ((rc = dev_upload(ix->allocs, ix->bytes, L.blk_max.data(), L.blk_max.size(), &blk_max, s))) return done(rc);
+    if ((rc = dev_upload(ix->allocs, ix->bytes, L.blk_first.data(), L.blk_first.size(), &blk_first, s)))
+        return done(rc);
+    if (flags & GS_KEEP_FORWARD) {
+        int64_t* frp = nullptr;
+        int32_t* ft = nullptr;
+        float* fw = nullptr;
+        if ((rc = dev_upload(ix->allocs, ix->bytes, r.row_ptr, (size_t)n_docs + 1, &frp, s))) return done(rc);
+        if ((rc = dev_upload(ix->allocs, ix->bytes, r.term, (size_t)nnz, &ft, s))) return done(rc);
+        if ((rc = dev_upload(ix->allocs, ix->bytes, r.w, (size_t)nnz, &fw, s))) return done(rc);
+        d.fwd_row_ptr = frp;
+        d.fwd_term = ft;
+        d.fwd_w = fw;
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(fail(GS_EHIP, std::string("upload: ") + hipGetErrorString(e)));
+    *out = ix;
+    return GS_OK;
+}
+
+int32_t gs_index_info(gs_index ix, gs_index_info_t* out) {
+    g_err.clear();
+    if (!ix || !out) return fail(GS_EINVAL, "null argument");
+    out->n_docs = ix->n_docs;
+    out->nnz = ix->nnz;
+    out->padded_nnz = ix->padded;
+    out->device_bytes = (int64_t)ix->bytes;
+    out->vocab_size = ix->vocab;
+    out->precision = ix->precision;
+    out->flags = ix->flags;
+    out->tile_grain = 1 << kGrainShift;
+    out->n_tiles = ix->n_grains;
+    return GS_OK;
+}
+
+void gs_free_index(gs_index ix) {
+    if (!ix) return;
+    DeviceGuard g(ix->device);
+    delete ix;
+}
+
+int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
+                        const float* q_weights, int64_t q_nnz, const int32_t* k, int32_t k_max, void* hip_stream,
+                        gs_batch* out) {
+    g_err.clear();
+    if (!out) return fail(GS_EINVAL, "out is null");
+    *out = nullptr;
+    if (!ix) return fail(GS_EINVAL, "index is null");
+    if (n_queries < 0) return fail(GS_EINVAL, "n_queries < 0");
+    if (k_max < 0 || k_max > GS_MAX_K) return fail(GS_EINVAL, "k_max must be in [0, GS_MAX_K]");
+    if (n_queries > 0 && !k) return fail(GS_EINVAL, "k is null");
+    for (int32_t q = 0; q < n_queries; q++)
+        if (k[q] < 0 || k[q] > k_max) return fail(GS_EINVAL, "k[" + std::to_string(q) + "] outside [0, k_max]");
+    Rows r{q_row_ptr, q_term_ids, q_weights, n_queries, {}, {}};
+    int32_t rc = check_rows(r, q_nnz, ix->vocab, kMaxQueryNnz, "queries");
+    if (rc != GS_OK) return rc;
+    DeviceGuard g(ix->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    gs_batch b = new (std::nothrow) gs_batch_s();
+    if (!b) return fail(GS_ENOMEM, "host allocation failed");
+    b->index = ix;
+    b->n_queries = n_queries;
+    b->k_max = k_max;
+    b->q_nnz = q_nnz;
+    auto done = [&](int32_t code) {
+        if (code != GS_OK) delete b;
+        return code;
+    };
+    std::vector<int64_t> rp(q_row_ptr ? q_row_ptr : nullptr, q_row_ptr ? q_row_ptr + n_queries + 1 : nullptr);
+    if (rp.empty()) rp.push_back(0);
+    std::vector<int32_t> w8((size_t)q_nnz), fshift((size_t)n_queries);
+    std::vector<float> delta((size_t)n_queries);
+    for (int32_t q = 0; q < n_queries; q++) {
+        uint64_t maxs = 0;
+        const int64_t m = rp[(size_t)q + 1] - rp[(size_t)q];
+        for (int64_t j = rp[(size_t)q]; j < rp[(size_t)q + 1]; j++) {
+            w8[(size_t)j] = q8(r.w[j]);
+            maxs += (uint64_t)w8[(size_t)j] * 255u;
+        }
+        if (ix->precision == kU8) {
+            int hb = 0;
+            while (hb < 64 && (maxs >> hb) != 0) hb++;
+            fshift[(size_t)q] = 32 + std::max(hb, kHistBits) - kHistBits;
+        } else {
+            fshift[(size_t)q] = kFirstShiftFloat;
+        }
+        // |approx - exact| <= delta * exact for bf16 weights with fp32 products and sums of m terms
+        const double u = std::ldexp(1.0, -24);
+        const double gm = (double)(m + 1) * u / (1.0 - (double)(m + 1) * u);
+        delta[(size_t)q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + gm) - 1.0) * (1.0 + 1e-6));
+    }
+    int64_t* d_rp = nullptr;
+    int32_t *d_t = nullptr, *d_w8 = nullptr, *d_k = nullptr, *d_fs = nullptr;
+    float *d_w = nullptr, *d_delta = nullptr;
+    size_t bytes = 0;
+    if ((rc = dev_upload(b->allocs, bytes, rp.data(), rp.size(), &d_rp, s))) return done(rc);
+    if ((rc = dev_upload(b->allocs, bytes, r.term, (size_t)q_nnz, &d_t, s))) return done(rc);
+    if ((rc = dev_upload(b->allocs, bytes, r.w, (size_t)q_nnz, &d_w, s))) return done(rc);
+    if ((rc = dev_upload(b->allocs, bytes, w8.data(), w8.size(), &d_w8, s))) return done(rc);
+    if ((rc = dev_upload(b->allocs, bytes, k, (size_t)n_queries, &d_k, s))) return done(rc);
+    if ((rc = dev_upload(b->allocs, bytes, fshift.data(), fshift.size(), &d_fs, s))) return done(rc);
+    if ((rc = dev_upload(b->allocs, bytes, delta.data(), delta.size(), &d_delta, s))) return done(rc);
+    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, (size_t)n_queries * 4, &b->diag, s))) return done(rc);
+    hipError_t e = hipMemsetAsync(b->diag, 0, (size_t)std::max(n_queries, 1) * 16, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(fail(GS_EHIP, std::string("batch upload: ") + hipGetErrorString(e)));
+    DevBatch& d = b->dev;
+    d.n_queries = n_queries;
+    d.k_max = k_max;
+    d.q_row_ptr = d_rp;
+    d.q_term = d_t;
+    d.q_w = d_w;
+    d.q_w8 = d_w8;
+    d.k = d_k;
+    d.first_shift = d_fs;
+    d.delta = d_delta;
+    *out = b;
+    return GS_OK;
+}
+
+void gs_batch_free(gs_batch b) {
+    if (!b) return;
+    DeviceGuard g(b->index ? b->index->device : 0);
+    delete b;
+}
+
+static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so) {
+    so->kernel = GS_KERNEL_TILED;
+    so->tile_shift = 14;
+    so->chunk = 256;
+    so->group = 4;
+    if (!o) return GS_OK;
+    for (int i = 0; i < 3; i++)
+        if (o->reserved[i] != 0) return fail(GS_EINVAL, "reserved option fields must be 0");
+    if (o->kernel < GS_KERNEL_AUTO || o->kernel > GS_KERNEL_SHARED) return fail(GS_EINVAL, "unknown kernel");
+    if (o->kernel != GS_KERNEL_AUTO) so->kernel = o->kernel;
+    if (so->kernel == GS_KERNEL_SHARED) return fail(GS_EUNSUPPORTED, "shared-traversal kernel not built yet");
+    if (so->kernel == GS_KERNEL_DOCPAR && !(ix->flags & GS_KEEP_FORWARD))
+        return fail(GS_EUNSUPPORTED, "document-parallel kernel needs an index built with GS_KEEP_FORWARD");
+    if (o->query_tile < 0) return fail(GS_EINVAL, "query_tile < 0");
+    switch (o->tile_docs) {
+        case 0: break;
+        case 8192: so->tile_shift = 13; break;
+        case 16384: so->tile_shift = 14; break;
+        case 32768: so->tile_shift = 15; break;
+        default: return fail(GS_EINVAL, "tile_docs must be 0, 8192, 16384 or 32768");
+    }
+    switch (o->chunk) {
+        case 0: break;
+        case 64: case 128: case 256: case 512: case 1024: so->chunk = o->chunk; break;
+        default: return fail(GS_EINVAL, "chunk must be 0, 64, 128, 256, 512 or 1024");
+    }
+    if (o->group < 0 || o->group > 8) return fail(GS_EINVAL, "group must be in [0, 8]");
+    if (o->group) so->group = o->group;
+    return GS_OK;
+}
+
+int32_t gs_workspace_size(gs_index ix, int32_t query_tile, const gs_search_opts* opts, size_t* bytes) {
+    g_err.clear();
+    if (!ix || !bytes) return fail(GS_EINVAL, "null argument");
+    if (query_tile < 1) return fail(GS_EINVAL, "query_tile < 1");
+    ScoreOpts so;
+    int32_t rc = resolve_opts(ix, opts, &so);
+    if (rc != GS_OK) return rc;
+    *bytes = workspace_bytes(ix->n_docs, query_tile, ix->precision);
+    return GS_OK;
+}
+
+int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspace_bytes_, int32_t* out_ids,
+                        void* out_scores, const gs_search_opts* opts, void* hip_stream) {
+    g_err.clear();
+    if (!ix || !b) return fail(GS_EINVAL, "null index or batch");
+    if (b->index != ix) return fail(GS_EINVAL, "batch was created for another index");
+    ScoreOpts so;
+    int32_t rc = resolve_opts(ix, opts, &so);
+    if (rc != GS_OK) return rc;
+    const int32_t nq = b->n_queries;
+    if (nq == 0 || b->k_max == 0) return GS_OK;
+    if (!out_ids || !out_scores) return fail(GS_EINVAL, "null output");
+    if (!workspace) return fail(GS_EINVAL, "null workspace");
+    int32_t qt = 1;
+    if (workspace_bytes(ix->n_docs, 1, ix->precision) > workspace_bytes_)
+        return fail(GS_ECAPACITY, "workspace smaller than gs_workspace_size(index, 1)");
+    {
+        int32_t lo = 1, hi = nq;
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo + 1) / 2;
+            if (workspace_bytes(ix->n_docs, mid, ix->precision) <= workspace_bytes_) lo = mid; else hi = mid - 1;
+        }
+        qt = lo;
+    }
+    if (opts && opts->query_tile > 0) qt = std::min(qt, opts->query_tile);
+    DeviceGuard g(ix->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    Workspace ws;
+    carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
+    for (int32_t q0 = 0; q0 < nq; q0 += qt) {
+        const int32_t n = std::min(qt, nq - q0);
+        hipError_t e = launch_clear(ws, n, s);
+        if (e == hipSuccess && ix->n_docs > 0) {
+            SpanRecorder rec(0, s);
+            if (so.kernel == GS_KERNEL_ATOMIC) e = launch_score_atomic(ix->dev, b->dev, q0, n, so, ws, s);
+            else if (so.kernel == GS_KERNEL_DOCPAR) e = launch_score_docpar(ix->dev, b->dev, q0, n, so, ws, s);
+            else e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s);
+            rec.end(s);
+        }
+        if (e == hipSuccess) {
+            SpanRecorder rec(1, s);
+            e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s);
+            rec.end(s);
+        }
+        if (e != hipSuccess) return fail(GS_EHIP, std::string("launch: ") + hipGetErrorString(e));
+    }
+    return GS_OK;
+}
+
+int32_t gs_search(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
+                  const float* q_weights, int64_t q_nnz, const int32_t* k, int32_t k_max, void* workspace,
+                  size_t workspace_bytes_, int32_t* out_ids, void* out_scores, const gs_search_opts* opts,
+                  void* hip_stream) {
+    gs_batch b = nullptr;
+    int32_t rc = gs_batch_create(ix, q_row_ptr, n_queries, q_term_ids, q_weights, q_nnz, k, k_max, hip_stream, &b);
+    if (rc != GS_OK) return rc;
+    rc = gs_search_batch(ix, b, workspace, workspace_bytes_, out_ids, out_scores, opts, hip_stream);
+    hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+    gs_batch_free(b);
+    if (rc == GS_OK && e != hipSuccess) rc = fail(GS_EHIP, std::string("search: ") + hipGetErrorString(e));
+    return rc;
+}
+
+int32_t gs_timing_enable(int32_t on) {
+    std::lock_guard<std::mutex> l(g_timing_mu);
+    g_timing_on = on != 0;
+    return GS_OK;
+}
+
+int32_t gs_timing_read(double* score_ms, int64_t* score_launches, double* select_ms, int64_t* select_launches) {
+    g_err.clear();
+    std::vector<TimedSpan> spans;
+    {
+        std::lock_guard<std::mutex> l(g_timing_mu);
+        spans.swap(g_spans);
+    }
+    double ms[2] = {0.0, 0.0};
+    int64_t cnt[2] = {0, 0};
+    hipError_t err = hipSuccess;
+    for (auto& sp : spans) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(sp.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, sp.a, sp.b);
+        if (e == hipSuccess) {
+            ms[sp.kind] += t;
+            cnt[sp.kind] += 1;
+        } else {
+            err = e;
+        }
+        (void)hipEventDestroy(sp.a);
+        (void)hipEventDestroy(sp.b);
+    }
+    if (score_ms) *score_ms = ms[0];
+    if (score_launches) *score_launches = cnt[0];
+    if (select_ms) *select_ms = ms[1];
+    if (select_launches) *select_launches = cnt[1];
+    if (err != hipSuccess) return fail(GS_EHIP, std::string("timing: ") + hipGetErrorString(err));
+    return GS_OK;
+}
+
+int32_t gs_batch_diagnostics(gs_batch b, int32_t* out) {
+    g_err.clear();
+    if (!b || !out) return fail(GS_EINVAL, "null argument");
+    if (b->n_queries == 0) return GS_OK;
+    DeviceGuard g(b->index->device);
+    GS_HIP(hipMemcpy(out, b->diag, (size_t)b->n_queries * 16, hipMemcpyDeviceToHost));
+    return GS_OK;
+}
+
+}  // extern "C"

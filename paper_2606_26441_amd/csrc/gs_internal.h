@@ -1,0 +1,107 @@
+// Internal declarations shared by the host side (gs_host.cpp) and the HIP
+// kernels (gs_score.hip, gs_topk.hip) of libgpusparse.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gs {
+
+constexpr int kWave = 64;             // CDNA wavefront
+constexpr int kBlock = 64;            // postings per padded block (one wavefront)
+constexpr int kGrainShift = 13;       // segment-table doc-tile granularity: 8192 docs
+constexpr int kMaxQueryNnz = 256;     // GS_MAX_QUERY_NNZ
+constexpr int kMaxK = 4096;           // GS_MAX_K
+constexpr int kHistBits = 11;         // selection digit width (first digit fused into scoring)
+constexpr int kHistBins = 1 << kHistBits;
+constexpr int kCandCap = 32768;       // candidates kept per query by the filter pass
+constexpr int kRefinePasses = 6;      // enough to resolve any 64-bit composite key
+constexpr int kFirstShiftFloat = 52;  // first digit of a float key: bits 30..20
+
+enum Precision { kFP32 = 0, kBF16 = 1, kU8 = 2 };
+
+// Index arrays on the device (plain pointers; passed by value to kernels).
+struct DevIndex {
+    int64_t n_docs;
+    int32_t vocab;
+    int32_t precision;
+    const int64_t* term_off;   // [V+1] start of each padded list
+    const int32_t* term_len;   // [V]   real postings per term
+    const int32_t* post_doc;   // [padded_nnz], -1 in padding
+    const void* post_w;        // [padded_nnz] float | bf16 bits (uint16) | uint8
+    const int32_t* tile_off;   // [V][n_grains+1] posting offset (relative to the list start)
+    int64_t n_grains;          // ceil(n_docs / 8192)
+    const int64_t* fwd_row_ptr;  // [N+1] forward rows (sorted by term), or null
+    const int32_t* fwd_term;
+    const float* fwd_w;
+};
+
+// A query batch on the device.
+struct DevBatch {
+    int32_t n_queries;
+    int32_t k_max;
+    const int64_t* q_row_ptr;  // [n+1]
+    const int32_t* q_term;     // [q_nnz], ascending within each query
+    const float* q_w;          // [q_nnz]
+    const int32_t* q_w8;       // [q_nnz] uint8 impacts as int (GS_U8), else null
+    const int32_t* k;          // [n]
+    const int32_t* first_shift;  // [n] position of the first selection digit in the composite key
+    const float* delta;        // [n] bf16 relative error bound per query (GS_BF16), else null
+};
+
+// Per-query selection state in the workspace.
+struct SelState {
+    unsigned long long prefix;  // bucket: composites c with (c >> shift) == (prefix >> shift)
+    unsigned long long lo;      // filter threshold (inclusive) once resolved
+    int32_t shift;
+    int32_t k_rem;              // still needed from the bucket
+    int32_t resolved;           // 0 refine, 1 filter with lo, 2 nothing to select (k == 0)
+    int32_t n_cand;             // candidates appended by the filter
+    int32_t passes;             // refinement passes over the score array
+    int32_t band;               // bf16: candidates inside the error band
+    int32_t overflow;           // candidate or band buffer overflow
+    int32_t need_band_pass;     // bf16: band reaches below the filter threshold
+    double tau;                 // bf16: band threshold on approximate scores
+};
+
+// Workspace carve-up for a tile of qt queries.
+struct Workspace {
+    uint32_t* scores;             // [qt][N] fp32 bits or int32
+    uint32_t* hist1;              // [qt][kHistBins]
+    uint32_t* hist_ref;           // [qt][kHistBins]
+    SelState* state;              // [qt]
+    unsigned long long* cand;     // [qt][kCandCap]
+    double* band_s;               // [qt][kCandCap] (bf16)
+    int32_t* band_id;             // [qt][kCandCap] (bf16)
+    int64_t* work_prefix;         // [qt * kMaxQueryNnz + 1] (atomic kernel)
+    int32_t* work_pair_q;         // [qt * kMaxQueryNnz]
+    int64_t ld;                   // row stride of the score arrays (n_docs rounded up to 64)
+};
+
+size_t workspace_bytes(int64_t n_docs, int32_t qt, int32_t precision);
+void carve_workspace(void* base, int64_t n_docs, int32_t qt, int32_t precision, Workspace* ws);
+
+struct ScoreOpts {
+    int kernel;
+    int tile_shift;   // doc tile of the TILED/SHARED kernels = 1 << tile_shift docs
+    int chunk;        // postings per work item
+    int group;
+};
+
+// ---- launchers (gs_score.hip) ----
+hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s);
+hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
+                              const ScoreOpts& o, const Workspace& ws, hipStream_t s);
+hipError_t launch_score_atomic(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
+                               const ScoreOpts& o, const Workspace& ws, hipStream_t s);
+hipError_t launch_score_docpar(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
+                               const ScoreOpts& o, const Workspace& ws, hipStream_t s);
+hipError_t launch_hist1(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
+                        const Workspace& ws, hipStream_t s);
+
+// ---- launchers (gs_topk.hip) ----
+hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
+                         const Workspace& ws, int32_t* out_ids, void* out_scores, int32_t* diag,
+                         hipStream_t s);
+
+}  // namespace gs

@@ -1,0 +1,463 @@
+// Scoring kernels: fill one score array per query with
+//   S[q][d] = sum over the query's terms t of w_q(t) * w_d(t)
+// (paper Sec. 4.1: the score decomposes into one scatter-add per query term).
+//
+// Three forms:
+//  * k_score_tiled  - term-parallel, work = (query, doc tile). Each query term's
+//    posting list is doc-sorted, so the postings that fall into a doc tile are
+//    one contiguous segment (found in the per-term segment table). The
+//    workgroup streams every segment of its query through coalesced loads and
+//    scatter-adds w_q * w_d into an LDS copy of the tile with LDS atomics, then
+//    writes the tile once (coalesced) and builds the histogram of the first
+//    selection digit. No global atomics, no zeroing pass. This is the
+//    "shared-memory accumulation" hybrid the paper names as future work (1).
+//  * k_score_atomic - term-parallel, work = (query, term, chunk of postings);
+//    global atomic adds into a zeroed score array, as in the paper's Sec. 5.2
+//    kernel (one program per query term looping over posting chunks), with
+//    long lists split into chunks so that head terms do not serialise.
+//  * k_score_docpar - document-parallel (Sec. 5.3): per (query, doc) a gather
+//    over the doc's forward row with the query's weights in a dense LDS table;
+//    each output cell is written once, no atomics.
+//
+// Weight forms: fp32; bf16 (stored as the upper 16 bits of the fp32 pattern,
+// widened exactly, fp32 products and accumulation); uint8 impacts with int32
+// products and accumulation (exact).
+#include <algorithm>
+#include <type_traits>
+
+#include "gs_internal.h"
+
+namespace gs {
+
+namespace {
+
+template <int P> struct WF;
+template <> struct WF<kFP32> {
+    using Acc = float;
+    static __device__ __forceinline__ float load(const void* p, int64_t i) { return ((const float*)p)[i]; }
+    static __device__ __forceinline__ float from_fp32(float w) { return w; }
+    static __device__ __forceinline__ float qweight(const DevBatch& qb, int64_t j) { return qb.q_w[j]; }
+    static __device__ __forceinline__ uint32_t bits(float v) { return __float_as_uint(v); }
+};
+template <> struct WF<kBF16> {
+    using Acc = float;
+    static __device__ __forceinline__ float load(const void* p, int64_t i) {
+        return __uint_as_float((uint32_t)((const uint16_t*)p)[i] << 16);
+    }
+    static __device__ __forceinline__ float from_fp32(float w) {
+        // round to nearest even on the upper 16 bits (weights are finite and >= 0)
+        uint32_t u = __float_as_uint(w);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return __uint_as_float(u & 0xffff0000u);
+    }
+    static __device__ __forceinline__ float qweight(const DevBatch& qb, int64_t j) { return qb.q_w[j]; }
+    static __device__ __forceinline__ uint32_t bits(float v) { return __float_as_uint(v); }
+};
+template <> struct WF<kU8> {
+    using Acc = int;
+    static __device__ __forceinline__ int load(const void* p, int64_t i) { return ((const uint8_t*)p)[i]; }
+    static __device__ __forceinline__ int from_fp32(float w) {
+        double x = __builtin_rint((double)w * 85.0);
+        return x > 255.0 ? 255 : (x > 0.0 ? (int)x : 0);
+    }
+    static __device__ __forceinline__ int qweight(const DevBatch& qb, int64_t j) { return qb.q_w8[j]; }
+    static __device__ __forceinline__ uint32_t bits(int v) { return (uint32_t)v; }
+};
+
+__device__ __forceinline__ unsigned long long comp_key(uint32_t key, uint32_t id) {
+    return ((unsigned long long)key << 32) | (unsigned long long)(~id);
+}
+
+__device__ __forceinline__ void lds_add(uint32_t* a, float v) { atomicAdd(reinterpret_cast<float*>(a), v); }
+__device__ __forceinline__ void lds_add(uint32_t* a, int v) { atomicAdd(reinterpret_cast<int*>(a), v); }
+__device__ __forceinline__ void glb_add(uint32_t* a, float v) { unsafeAtomicAdd(reinterpret_cast<float*>(a), v); }
+__device__ __forceinline__ void glb_add(uint32_t* a, int v) { atomicAdd(reinterpret_cast<int*>(a), v); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Write a finished LDS tile to the score array and add its first-digit
+// histogram (composite key (score bits, ~doc id), digit at first_shift).
+template <int BS>
+__device__ __forceinline__ void flush_tile(const uint32_t* acc, uint32_t* hist, int tile_n, int64_t base,
+                                           uint32_t* Sq, int fs, uint32_t* hist_out) {
+    const int tid = threadIdx.x;
+    const int n4 = tile_n >> 2;
+    for (int i = tid; i < n4; i += BS) {
+        uint4 v = reinterpret_cast<const uint4*>(acc)[i];
+        reinterpret_cast<uint4*>(Sq)[i] = v;
+        const uint32_t d0 = (uint32_t)(base + 4 * i);
+        atomicAdd(&hist[(comp_key(v.x, d0 + 0) >> fs) & (kHistBins - 1)], 1u);
+        atomicAdd(&hist[(comp_key(v.y, d0 + 1) >> fs) & (kHistBins - 1)], 1u);
+        atomicAdd(&hist[(comp_key(v.z, d0 + 2) >> fs) & (kHistBins - 1)], 1u);
+        atomicAdd(&hist[(comp_key(v.w, d0 + 3) >> fs) & (kHistBins - 1)], 1u);
+    }
+    for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
+        uint32_t v = acc[i];
+        Sq[i] = v;
+        atomicAdd(&hist[(comp_key(v, (uint32_t)(base + i)) >> fs) & (kHistBins - 1)], 1u);
+    }
+    __syncthreads();
+    for (int b = tid; b < kHistBins; b += BS)
+        if (hist[b]) atomicAdd(&hist_out[b], hist[b]);
+}
+
+// ------------------------------------------------------------- tiled --
+
+template <int P, int TS, int CH>
+__global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
+                                                     int64_t ld, uint32_t* __restrict__ hist1) {
+    constexpr int BS = 512, NW = BS / kWave, TILE = 1 << TS, U = CH / kWave, GPT = TS - kGrainShift;
+    using Acc = typename WF<P>::Acc;
+    extern __shared__ __align__(16) uint32_t lds[];
+    uint32_t* acc = lds;            // [TILE]
+    uint32_t* hist = lds + TILE;    // [kHistBins]
+    __shared__ int64_t seg_beg[kMaxQueryNnz];
+    __shared__ int32_t seg_len[kMaxQueryNnz];
+    __shared__ int32_t seg_cpre[kMaxQueryNnz + 1];
+    __shared__ Acc seg_w[kMaxQueryNnz];
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int ql = blockIdx.y, q = q0 + ql;
+    const int64_t N = ix.n_docs;
+    const int64_t base = (int64_t)blockIdx.x << TS;
+    const int tile_n = (int)min((int64_t)TILE, N - base);
+
+    for (int i = tid; i < TILE; i += BS) acc[i] = 0u;
+    for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
+
+    const int64_t qa = qb.q_row_ptr[q];
+    const int nq = (int)(qb.q_row_ptr[q + 1] - qa);
+    const int64_t g0 = (int64_t)blockIdx.x << GPT;
+    const int64_t g1 = min(g0 + (int64_t)(1 << GPT), ix.n_grains);
+    for (int t = tid; t < nq; t += BS) {
+        const int term = qb.q_term[qa + t];
+        const int32_t* row = ix.tile_off + (int64_t)term * (ix.n_grains + 1);
+        const int a = row[g0], b = row[g1];
+        seg_beg[t] = ix.term_off[term] + a;
+        seg_len[t] = b - a;
+        seg_w[t] = WF<P>::qweight(qb, qa + t);
+    }
+    __syncthreads();
+    if (wave == 0) {
+        int c[4];
+        int s = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int t = lane * 4 + u;
+            c[u] = t < nq ? (seg_len[t] + CH - 1) / CH : 0;
+            s += c[u];
+        }
+        int incl = s;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int v = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += v;
+        }
+        int run = incl - s;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            seg_cpre[lane * 4 + u] = run;
+            run += c[u];
+        }
+        const int total = __shfl(incl, kWave - 1, kWave);
+        if (lane == 0) seg_cpre[kMaxQueryNnz] = total;
+    }
+    __syncthreads();
+
+    const int total = seg_cpre[nq];
+    for (int c = wave; c < total; c += NW) {
+        int lo = 0, hi = nq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (seg_cpre[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        const int off = (c - seg_cpre[lo]) * CH;
+        const int n = min(CH, seg_len[lo] - off);
+        const int64_t p0 = seg_beg[lo] + off;
+        const Acc wq = seg_w[lo];
+        int doc[U];
+        Acc w[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int i = lane + u * kWave;
+            if (i < n) {
+                doc[u] = __builtin_nontemporal_load(ix.post_doc + p0 + i);
+                w[u] = WF<P>::load(ix.post_w, p0 + i);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int i = lane + u * kWave;
+            if (i < n) lds_add(&acc[doc[u] - base], wq * w[u]);
+        }
+    }
+    __syncthreads();
+    flush_tile<BS>(acc, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
+                   hist1 + (int64_t)ql * kHistBins);
+}
+
+// ------------------------------------------------------------ atomic --
+
+// Exclusive prefix of posting chunks over the (query, term) pairs of a query tile.
+__global__ __launch_bounds__(1024) void k_pair_prefix(DevIndex ix, DevBatch qb, int32_t q0, int32_t qt, int chunk,
+                                                      int64_t* __restrict__ prefix, int32_t* __restrict__ pair_q) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t a0 = qb.q_row_ptr[q0];
+    const int64_t np = qb.q_row_ptr[q0 + qt] - a0;
+    const int64_t per = (np + 1023) / 1024;
+    const int64_t lo = min(np, tid * per), hi = min(np, lo + per);
+    int64_t s = 0;
+    for (int64_t p = lo; p < hi; p++) {
+        const int term = qb.q_term[a0 + p];
+        const int64_t padded = ix.term_off[term + 1] - ix.term_off[term];
+        s += (padded + chunk - 1) / chunk;
+    }
+    part[tid] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int64_t v = tid >= d ? part[tid - d] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = part[tid] - s;
+    int ql = 0;
+    for (int64_t p = lo; p < hi; p++) {
+        while (qb.q_row_ptr[q0 + ql + 1] - a0 <= p) ql++;
+        prefix[p] = run;
+        pair_q[p] = ql;
+        const int term = qb.q_term[a0 + p];
+        const int64_t padded = ix.term_off[term + 1] - ix.term_off[term];
+        run += (padded + chunk - 1) / chunk;
+    }
+    if (tid == 1023) prefix[np] = part[1023];
+}
+
+template <int P, int CH>
+__global__ __launch_bounds__(256) void k_score_atomic(DevIndex ix, DevBatch qb, int32_t q0, int32_t qt,
+                                                      const int64_t* __restrict__ prefix,
+                                                      const int32_t* __restrict__ pair_q, uint32_t* __restrict__ S,
+                                                      int64_t ld) {
+    constexpr int NW = 256 / kWave, U = CH / kWave;
+    using Acc = typename WF<P>::Acc;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t a0 = qb.q_row_ptr[q0];
+    const int64_t np = qb.q_row_ptr[q0 + qt] - a0;
+    const int64_t total = prefix[np];
+    for (int64_t c = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6); c < total; c += (int64_t)gridDim.x * NW) {
+        int64_t lo = 0, hi = np - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        const int term = qb.q_term[a0 + lo];
+        const Acc wq = WF<P>::qweight(qb, a0 + lo);
+        const int64_t off = (c - prefix[lo]) * (int64_t)CH;
+        const int64_t p0 = ix.term_off[term] + off;
+        const int n = (int)min((int64_t)CH, ix.term_off[term + 1] - p0);  // a list ends on a 64-posting block
+        uint32_t* Sq = S + (int64_t)pair_q[lo] * ld;
+        int doc[U];
+        Acc w[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int i = lane + u * kWave;
+            doc[u] = -1;
+            if (i < n) {
+                doc[u] = ix.post_doc[p0 + i];
+                w[u] = WF<P>::load(ix.post_w, p0 + i);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (doc[u] >= 0) glb_add(&Sq[doc[u]], wq * w[u]);
+    }
+}
+
+// ------------------------------------------------------------ docpar --
+
+template <int P>
+__global__ __launch_bounds__(1024) void k_score_docpar(DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
+                                                       int64_t ld, int docs_per_block) {
+    using Acc = typename WF<P>::Acc;
+    extern __shared__ __align__(16) uint32_t table[];  // [vocab] query weights (dense)
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int ql = blockIdx.y, q = q0 + ql;
+    for (int i = tid; i < ix.vocab; i += 1024) table[i] = 0u;
+    __syncthreads();
+    const int64_t qa = qb.q_row_ptr[q], qn = qb.q_row_ptr[q + 1] - qa;
+    for (int t = tid; t < qn; t += 1024) {
+        Acc v = WF<P>::qweight(qb, qa + t);
+        table[qb.q_term[qa + t]] = WF<P>::bits(v);
+    }
+    __syncthreads();
+    const Acc* tab = reinterpret_cast<const Acc*>(table);
+    const int64_t d0 = (int64_t)blockIdx.x * docs_per_block;
+    const int64_t d1 = min(ix.n_docs, d0 + docs_per_block);
+    uint32_t* Sq = S + (int64_t)ql * ld;
+    for (int64_t d = d0 + wave; d < d1; d += 16) {
+        const int64_t a = ix.fwd_row_ptr[d], b = ix.fwd_row_ptr[d + 1];
+        Acc s = 0;
+        for (int64_t j = a + lane; j < b; j += kWave) s += tab[ix.fwd_term[j]] * WF<P>::from_fp32(ix.fwd_w[j]);
+        s = wave_sum(s);
+        if (lane == 0) Sq[d] = WF<P>::bits(s);
+    }
+}
+
+// ------------------------------------------------------ hist / clear --
+
+__global__ __launch_bounds__(512) void k_hist1(DevBatch qb, int32_t q0, int64_t N, const uint32_t* __restrict__ S,
+                                               int64_t ld, int per_block, uint32_t* __restrict__ hist1) {
+    __shared__ uint32_t hist[kHistBins];
+    const int tid = threadIdx.x, ql = blockIdx.y;
+    for (int i = tid; i < kHistBins; i += 512) hist[i] = 0u;
+    __syncthreads();
+    const int fs = qb.first_shift[q0 + ql];
+    const int64_t d0 = (int64_t)blockIdx.x * per_block, d1 = min(N, d0 + per_block);
+    const uint32_t* Sq = S + (int64_t)ql * ld;
+    for (int64_t d = d0 + tid; d < d1; d += 512)
+        atomicAdd(&hist[(comp_key(Sq[d], (uint32_t)d) >> fs) & (kHistBins - 1)], 1u);
+    __syncthreads();
+    for (int b = tid; b < kHistBins; b += 512)
+        if (hist[b]) atomicAdd(&hist1[(int64_t)ql * kHistBins + b], hist[b]);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t fill_u32(void* p, int64_t n_words, hipStream_t s) {
+    if (n_words <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n_words + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n_words, 0u);
+    return hipGetLastError();
+}
+
+template <typename F>
+hipError_t by_precision(int p, F f) {
+    switch (p) {
+        case kFP32: return f(std::integral_constant<int, kFP32>());
+        case kBF16: return f(std::integral_constant<int, kBF16>());
+        case kU8: return f(std::integral_constant<int, kU8>());
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int P, int TS>
+hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, const Workspace& ws,
+                       int64_t ld, hipStream_t s) {
+    const dim3 grid((unsigned)((ix.n_docs + (1 << TS) - 1) >> TS), (unsigned)qt);
+    const size_t lds = (size_t)((1 << TS) + kHistBins) * 4;
+    if (lds > 65536) {
+        static const hipError_t attr = [&] {
+            hipError_t e = hipSuccess;
+            const void* fns[] = {(const void*)k_score_tiled<P, TS, 64>, (const void*)k_score_tiled<P, TS, 128>,
+                                 (const void*)k_score_tiled<P, TS, 256>, (const void*)k_score_tiled<P, TS, 512>,
+                                 (const void*)k_score_tiled<P, TS, 1024>};
+            for (const void* f : fns)
+                if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            return e;
+        }();
+        if (attr != hipSuccess) return attr;
+    }
+    switch (chunk) {
+        case 64: hipLaunchKernelGGL((k_score_tiled<P, TS, 64>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
+        case 128: hipLaunchKernelGGL((k_score_tiled<P, TS, 128>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
+        case 256: hipLaunchKernelGGL((k_score_tiled<P, TS, 256>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
+        case 512: hipLaunchKernelGGL((k_score_tiled<P, TS, 512>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
+        case 1024: hipLaunchKernelGGL((k_score_tiled<P, TS, 1024>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t score_ld(int64_t n_docs) { return (n_docs + 63) / 64 * 64; }
+
+hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s) {
+    hipError_t e = fill_u32(ws.hist1, (int64_t)qt * kHistBins, s);
+    if (e == hipSuccess) e = fill_u32(ws.hist_ref, (int64_t)qt * kHistBins, s);
+    if (e == hipSuccess) e = fill_u32(ws.state, (int64_t)qt * sizeof(SelState) / 4, s);
+    return e;
+}
+
+hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const ScoreOpts& o,
+                              const Workspace& ws, hipStream_t s) {
+    const int64_t ld = score_ld(ix.n_docs);
+    return by_precision(ix.precision, [&](auto pc) -> hipError_t {
+        constexpr int P = decltype(pc)::value;
+        switch (o.tile_shift) {
+            case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, ws, ld, s);
+            case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, ws, ld, s);
+            case 15: return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, ws, ld, s);
+        }
+        return hipErrorInvalidValue;
+    });
+}
+
+hipError_t launch_score_atomic(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const ScoreOpts& o,
+                               const Workspace& ws, hipStream_t s) {
+    const int64_t ld = score_ld(ix.n_docs);
+    hipError_t e = fill_u32(ws.scores, (int64_t)qt * ld, s);
+    if (e != hipSuccess) return e;
+    int64_t* prefix = ws.work_prefix;
+    int32_t* pair_q = ws.work_pair_q;
+    hipLaunchKernelGGL(k_pair_prefix, dim3(1), dim3(1024), 0, s, ix, qb, q0, qt, o.chunk, prefix, pair_q);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const dim3 grid(2048);
+    e = by_precision(ix.precision, [&](auto pc) -> hipError_t {
+        constexpr int P = decltype(pc)::value;
+        switch (o.chunk) {
+            case 64: hipLaunchKernelGGL((k_score_atomic<P, 64>), grid, dim3(256), 0, s, ix, qb, q0, qt, prefix, pair_q, ws.scores, ld); break;
+            case 128: hipLaunchKernelGGL((k_score_atomic<P, 128>), grid, dim3(256), 0, s, ix, qb, q0, qt, prefix, pair_q, ws.scores, ld); break;
+            case 256: hipLaunchKernelGGL((k_score_atomic<P, 256>), grid, dim3(256), 0, s, ix, qb, q0, qt, prefix, pair_q, ws.scores, ld); break;
+            case 512: hipLaunchKernelGGL((k_score_atomic<P, 512>), grid, dim3(256), 0, s, ix, qb, q0, qt, prefix, pair_q, ws.scores, ld); break;
+            case 1024: hipLaunchKernelGGL((k_score_atomic<P, 1024>), grid, dim3(256), 0, s, ix, qb, q0, qt, prefix, pair_q, ws.scores, ld); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    return launch_hist1(ix, qb, q0, qt, ws, s);
+}
+
+hipError_t launch_score_docpar(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const ScoreOpts& o,
+                               const Workspace& ws, hipStream_t s) {
+    (void)o;
+    const int64_t ld = score_ld(ix.n_docs);
+    const int per = 4096;
+    const dim3 grid((unsigned)((ix.n_docs + per - 1) / per), (unsigned)qt);
+    const size_t lds = (size_t)ix.vocab * 4;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;  // dense query table must fit one CU's LDS
+    hipError_t e = by_precision(ix.precision, [&](auto pc) -> hipError_t {
+        constexpr int P = decltype(pc)::value;
+        if (lds > 65536) {
+            const hipError_t a = hipFuncSetAttribute((const void*)k_score_docpar<P>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (a != hipSuccess) return a;
+        }
+        hipLaunchKernelGGL((k_score_docpar<P>), grid, dim3(1024), lds, s, ix, qb, q0, ws.scores, ld, per);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    return launch_hist1(ix, qb, q0, qt, ws, s);
+}
+
+hipError_t launch_hist1(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const Workspace& ws,
+                        hipStream_t s) {
+    const int64_t ld = score_ld(ix.n_docs);
+    const int per = 65536;
+    const dim3 grid((unsigned)((ix.n_docs + per - 1) / per), (unsigned)qt);
+    hipLaunchKernelGGL(k_hist1, grid, dim3(512), 0, s, qb, q0, ix.n_docs, (const uint32_t*)ws.scores, ld, per,
+                       ws.hist1);
+    return hipGetLastError();
+}
+
+}  // namespace gs

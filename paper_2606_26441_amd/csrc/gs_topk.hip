@@ -1,0 +1,487 @@
+// Exact per-query top-k over the score arrays (paper Sec. 4.2: a top-k over
+// each query's accumulator row; Sec. 4.3: the result is exact).
+//
+// Every document is ranked by the 64-bit composite key
+//     c = (score bits << 32) | (uint32)~doc_id
+// Non-negative fp32 and int32 scores are monotone in their bit patterns, and
+// ~id reverses the id order, so "c descending" is exactly "score descending,
+// then doc id ascending", and all composites are distinct: the k largest
+// composites are the unique answer, ties included.
+//
+// Pipeline for a tile of queries (all launches fixed, no host round trip):
+//  1. the first 11-bit digit histogram (built by the scoring kernel);
+//  2. k_select_first: find the digit bucket holding the k-th composite; if the
+//     composites at or above that bucket fit the candidate buffer the query is
+//     resolved, otherwise
+//  3. k_refine_hist / k_refine_select (up to six rounds): radix-select refinement
+//     over the full score array, 11 more bits per round, only for unresolved
+//     queries (a degenerate distribution such as a query matching fewer than k
+//     documents, where the answer is decided by doc ids);
+//  4. k_filter: append every composite >= the threshold to the candidate buffer
+//     (wavefront ballot + popcount for the append slot);
+//  5. k_final: radix select on the candidates (8-bit digits, LDS histograms) for
+//     the exact k-th composite, gather the k winners and place each one by its
+//     rank among them (one pass of comparisons, no sort network needed).
+// bf16 form: k_final also derives the error band of the k-th approximate score
+// and rescores every candidate in the band in fp64 from the fp32 forward rows
+// (ascending term order); k_band_filter / k_band_final handle the rare case in
+// which the band reaches below the candidate threshold.
+#include "gs_internal.h"
+
+namespace gs {
+
+namespace {
+
+__device__ __forceinline__ unsigned long long comp_key(uint32_t key, uint32_t id) {
+    return ((unsigned long long)key << 32) | (unsigned long long)(~id);
+}
+
+// One wavefront walks a kHistBins histogram from the top bin down and finds
+// the bin d holding the need-th largest element: above(d) < need <= above(d)+h[d].
+// Returns d; *above receives the count of elements in bins above d.
+__device__ int hist_walk(const uint32_t* h, uint32_t need, uint32_t* above) {
+    const int lane = threadIdx.x & (kWave - 1);
+    constexpr int PER = kHistBins / kWave;
+    const int top = kHistBins - 1 - lane * PER;
+    uint32_t s = 0;
+    for (int j = 0; j < PER; j++) s += h[top - j];
+    uint32_t incl = s;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += v;
+    }
+    const uint32_t excl = incl - s;
+    const unsigned long long m = __ballot(excl < need && need <= incl);
+    const int owner = m ? __ffsll((long long)m) - 1 : kWave - 1;
+    int dsel = 0;
+    uint32_t ab = 0;
+    if (lane == owner) {
+        uint32_t run = excl;
+        dsel = top - (PER - 1);
+        ab = run;
+        for (int j = 0; j < PER; j++) {
+            const uint32_t c = h[top - j];
+            if (run + c >= need) { dsel = top - j; ab = run; break; }
+            run += c;
+        }
+    }
+    dsel = __shfl(dsel, owner, kWave);
+    *above = __shfl(ab, owner, kWave);
+    return dsel;
+}
+
+__device__ __forceinline__ int64_t kq_of(const DevBatch& qb, int q, int64_t N) {
+    return min((int64_t)qb.k[q], N);
+}
+
+__global__ __launch_bounds__(64) void k_select_first(DevBatch qb, int32_t q0, int64_t N, int precision,
+                                                     const uint32_t* __restrict__ hist1, SelState* __restrict__ state) {
+    const int ql = blockIdx.x, q = q0 + ql;
+    SelState* st = state + ql;
+    const int64_t kq = kq_of(qb, q, N);
+    if (kq == 0) {
+        if (threadIdx.x == 0) st->resolved = 2;
+        return;
+    }
+    const uint32_t* h = hist1 + (int64_t)ql * kHistBins;
+    uint32_t above;
+    const int d = hist_walk(h, (uint32_t)kq, &above);
+    if (threadIdx.x != 0) return;
+    const int fs = qb.first_shift[q];
+    const int64_t ge = (int64_t)above + h[d];
+    if (precision == kBF16 && d > 0 && ge + h[d - 1] <= kCandCap) {
+        // one bin lower: the bf16 error band below the k-th score then lies inside the candidates
+        st->resolved = 1;
+        st->lo = (unsigned long long)(d - 1) << fs;
+    } else if (ge <= kCandCap) {
+        st->resolved = 1;
+        st->lo = (unsigned long long)d << fs;
+    } else {
+        st->resolved = 0;
+        st->prefix = (unsigned long long)d << fs;
+        st->shift = fs;
+        st->k_rem = (int32_t)(kq - above);
+    }
+}
+
+__global__ __launch_bounds__(512) void k_refine_hist(int32_t q0, int64_t N, const uint32_t* __restrict__ S, int64_t ld,
+                                                     int per_block, const SelState* __restrict__ state,
+                                                     uint32_t* __restrict__ hist_ref) {
+    __shared__ uint32_t hist[kHistBins];
+    const int ql = blockIdx.y;
+    const SelState st = state[ql];
+    if (st.resolved != 0) return;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kHistBins; i += 512) hist[i] = 0u;
+    __syncthreads();
+    const int shift = st.shift, nshift = max(shift - kHistBits, 0);
+    const unsigned long long want = st.prefix >> shift;
+    const unsigned long long mask = (1ull << (shift - nshift)) - 1ull;
+    const int64_t d0 = (int64_t)blockIdx.x * per_block, d1 = min(N, d0 + per_block);
+    const uint32_t* Sq = S + (int64_t)ql * ld;
+    for (int64_t d = d0 + tid; d < d1; d += 512) {
+        const unsigned long long c = comp_key(Sq[d], (uint32_t)d);
+        if ((c >> shift) == want) atomicAdd(&hist[(c >> nshift) & mask], 1u);
+    }
+    __syncthreads();
+    for (int b = tid; b < kHistBins; b += 512)
+        if (hist[b]) atomicAdd(&hist_ref[(int64_t)ql * kHistBins + b], hist[b]);
+}
+
+__global__ __launch_bounds__(64) void k_refine_select(DevBatch qb, int32_t q0, int64_t N,
+                                                      uint32_t* __restrict__ hist_ref, SelState* __restrict__ state) {
+    const int ql = blockIdx.x, q = q0 + ql;
+    SelState* st = state + ql;
+    if (st->resolved != 0) return;
+    uint32_t* h = hist_ref + (int64_t)ql * kHistBins;
+    const int64_t kq = kq_of(qb, q, N);
+    uint32_t above;
+    const int d = hist_walk(h, (uint32_t)st->k_rem, &above);
+    const uint32_t hd = h[d];
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHistBins; i += 64) h[i] = 0u;
+    if (threadIdx.x != 0) return;
+    const int nshift = max(st->shift - kHistBits, 0);
+    const unsigned long long prefix = st->prefix | ((unsigned long long)d << nshift);
+    const int32_t k_rem = st->k_rem - (int32_t)above;
+    st->passes += 1;
+    if ((kq - k_rem) + (int64_t)hd <= kCandCap) {
+        st->resolved = 1;
+        st->lo = prefix;
+    } else {
+        st->prefix = prefix;
+        st->shift = nshift;
+        st->k_rem = k_rem;
+    }
+}
+
+__global__ __launch_bounds__(512) void k_filter(int32_t q0, int64_t N, const uint32_t* __restrict__ S, int64_t ld,
+                                                int per_block, SelState* __restrict__ state,
+                                                unsigned long long* __restrict__ cand) {
+    const int ql = blockIdx.y;
+    SelState* st = state + ql;
+    if (st->resolved != 1) return;
+    const unsigned long long lo = st->lo;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int64_t d0 = (int64_t)blockIdx.x * per_block, d1 = min(N, d0 + per_block);
+    const uint32_t* Sq = S + (int64_t)ql * ld;
+    unsigned long long* C = cand + (int64_t)ql * kCandCap;
+    for (int64_t wb = d0 + wave * kWave; wb < d1; wb += 512) {
+        const int64_t d = wb + lane;
+        unsigned long long c = 0;
+        bool take = false;
+        if (d < d1) {
+            c = comp_key(Sq[d], (uint32_t)d);
+            take = c >= lo;
+        }
+        const unsigned long long m = __ballot(take);
+        if (m == 0) continue;
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(&st->n_cand, __popcll(m));
+        slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
+        if (take) {
+            if (slot < kCandCap) C[slot] = c;
+            else st->overflow = 1;
+        }
+    }
+}
+
+// fp64 rescoring of one document (forward row sorted by term) against the
+// query held in LDS (terms ascending): ascending-term sum of exact products.
+__device__ double rescore_f64(const DevIndex& ix, int64_t doc, const int32_t* qt, const float* qw, int nq) {
+    const int64_t a = ix.fwd_row_ptr[doc], b = ix.fwd_row_ptr[doc + 1];
+    double s = 0.0;
+    int j = 0;
+    for (int64_t i = a; i < b && j < nq; i++) {
+        const int t = ix.fwd_term[i];
+        while (j < nq && qt[j] < t) j++;
+        if (j < nq && qt[j] == t) s += (double)qw[j] * (double)ix.fwd_w[i];
+    }
+    return s;
+}
+
+// Rank band members by (fp64 score desc, id asc); write the first kq.
+__device__ void rank_band(const double* bs, const int32_t* bid, int nb, int64_t kq, int32_t* ids, double* sc) {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        const double si = bs[i];
+        const int32_t di = bid[i];
+        int r = 0;
+        for (int j = 0; j < nb; j++) {
+            const double sj = bs[j];
+            r += (sj > si) || (sj == si && bid[j] < di);
+        }
+        if (r < kq) { ids[r] = di; sc[r] = si; }
+    }
+}
+
+__device__ __forceinline__ double band_tau(float sk, float delta) {
+    // every true top-k doc has approx >= s_k*(1-delta) >= approx_k*(1-delta)/(1+delta)
+    const double d = (double)delta;
+    return (double)sk * (1.0 - d) / (1.0 + d) * (1.0 - 1e-12);
+}
+
+template <int P>
+__global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_t q0, SelState* __restrict__ state,
+                                                const unsigned long long* __restrict__ cand,
+                                                double* __restrict__ band_s, int32_t* __restrict__ band_id,
+                                                int32_t* __restrict__ out_ids, void* __restrict__ out_scores) {
+    __shared__ unsigned long long sel[kMaxK];
+    __shared__ uint32_t hist[256];
+    __shared__ int sh_d, sh_cnt;
+    __shared__ uint32_t sh_above;
+    __shared__ int32_t sq_t[kMaxQueryNnz];
+    __shared__ float sq_w[kMaxQueryNnz];
+    const int tid = threadIdx.x;
+    const int ql = blockIdx.x, q = q0 + ql;
+    SelState* st = state + ql;
+    const int64_t kq = kq_of(qb, q, ix.n_docs);
+    const int kmax = qb.k_max;
+    int32_t* ids = out_ids + (int64_t)q * kmax;
+    for (int i = tid; i < kmax; i += 1024) {
+        if (i >= kq) {
+            ids[i] = -1;
+            if (P == kBF16) ((double*)out_scores)[(int64_t)q * kmax + i] = 0.0;
+            else ((uint32_t*)out_scores)[(int64_t)q * kmax + i] = 0u;
+        }
+    }
+    if (kq == 0) return;
+    const int n = min(st->n_cand, kCandCap);
+    const unsigned long long* C = cand + (int64_t)ql * kCandCap;
+
+    // radix select of the kq-th largest composite among the n candidates
+    unsigned long long prefix = 0;
+    int shift = 64;
+    uint32_t need = (uint32_t)kq;
+    if (n > kq) {
+        while (shift > 0) {
+            const int nshift = shift - 8;
+            for (int i = tid; i < 256; i += 1024) hist[i] = 0u;
+            __syncthreads();
+            for (int i = tid; i < n; i += 1024) {
+                const unsigned long long c = C[i];
+                if (shift == 64 || (c >> shift) == (prefix >> shift)) atomicAdd(&hist[(c >> nshift) & 255ull], 1u);
+            }
+            __syncthreads();
+            if (tid < kWave) {
+                // 256 bins, 4 per lane, walked from the top
+                const int lane = tid;
+                uint32_t s = 0;
+                for (int j = 0; j < 4; j++) s += hist[255 - lane * 4 - j];
+                uint32_t incl = s;
+                for (int dd = 1; dd < kWave; dd <<= 1) {
+                    const uint32_t v = __shfl_up(incl, dd, kWave);
+                    if (lane >= dd) incl += v;
+                }
+                const uint32_t excl = incl - s;
+                const unsigned long long m = __ballot(excl < need && need <= incl);
+                const int owner = m ? __ffsll((long long)m) - 1 : kWave - 1;
+                if (lane == owner) {
+                    uint32_t run = excl;
+                    int dsel = 255 - lane * 4 - 3;
+                    uint32_t ab = run;
+                    for (int j = 0; j < 4; j++) {
+                        const uint32_t c = hist[255 - lane * 4 - j];
+                        if (run + c >= need) { dsel = 255 - lane * 4 - j; ab = run; break; }
+                        run += c;
+                    }
+                    sh_d = dsel;
+                    sh_above = ab;
+                }
+            }
+            __syncthreads();
+            const int d = sh_d;
+            need -= sh_above;
+            prefix |= (unsigned long long)d << nshift;
+            shift = nshift;
+            const uint32_t hd = hist[d];
+            __syncthreads();
+            if (hd == need) break;
+        }
+    }
+    // gather the kq winners: composites whose bits above `shift` are >= the prefix's
+    if (tid == 0) sh_cnt = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) {
+        const unsigned long long c = C[i];
+        const bool win = (shift == 64) || (shift == 0 ? c >= prefix : (c >> shift) >= (prefix >> shift));
+        if (win) {
+            const int pos = atomicAdd(&sh_cnt, 1);
+            if (pos < kMaxK) sel[pos] = c;
+        }
+    }
+    __syncthreads();
+    const int m = min(sh_cnt, kMaxK);
+    if (P != kBF16) {
+        for (int i = tid; i < m; i += 1024) {
+            const unsigned long long c = sel[i];
+            int r = 0;
+            for (int j = 0; j < m; j++) r += sel[j] > c;
+            if (r < kq) {
+                ids[r] = (int32_t)(~(uint32_t)c);
+                ((uint32_t*)out_scores)[(int64_t)q * kmax + r] = (uint32_t)(c >> 32);
+            }
+        }
+        return;
+    }
+    // bf16: exact k-th approximate score, then the error band and fp64 rescoring
+    __shared__ unsigned long long sh_min;
+    if (tid == 0) sh_min = ~0ull;
+    __syncthreads();
+    for (int i = tid; i < m; i += 1024) atomicMin(&sh_min, sel[i]);
+    const int64_t qa = qb.q_row_ptr[q];
+    const int nq = (int)(qb.q_row_ptr[q + 1] - qa);
+    for (int i = tid; i < nq; i += 1024) {
+        sq_t[i] = qb.q_term[qa + i];
+        sq_w[i] = qb.q_w[qa + i];
+    }
+    __syncthreads();
+    const float sk = __uint_as_float((uint32_t)(sh_min >> 32));
+    const double tau = band_tau(sk, qb.delta[q]);
+    const unsigned long long lo = st->lo;
+    const double lo_val = (double)__uint_as_float((uint32_t)(lo >> 32));
+    const bool inside = ((uint32_t)lo == 0u) ? (lo_val <= tau) : (lo_val < tau);
+    if (!inside) {
+        if (tid == 0) {
+            st->need_band_pass = 1;
+            st->tau = tau;
+        }
+        return;
+    }
+    double* bs = band_s + (int64_t)ql * kCandCap;
+    int32_t* bid = band_id + (int64_t)ql * kCandCap;
+    if (tid == 0) sh_cnt = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) {
+        const unsigned long long c = C[i];
+        if ((double)__uint_as_float((uint32_t)(c >> 32)) >= tau) {
+            const int pos = atomicAdd(&sh_cnt, 1);
+            const int32_t doc = (int32_t)(~(uint32_t)c);
+            bid[pos] = doc;
+            bs[pos] = rescore_f64(ix, doc, sq_t, sq_w, nq);
+        }
+    }
+    __syncthreads();
+    const int nb = sh_cnt;
+    if (tid == 0) st->band = nb;
+    __threadfence_block();
+    __syncthreads();
+    rank_band(bs, bid, nb, kq, ids, (double*)out_scores + (int64_t)q * kmax);
+}
+
+__global__ __launch_bounds__(512) void k_band_filter(int32_t q0, int64_t N, const uint32_t* __restrict__ S,
+                                                     int64_t ld, int per_block, SelState* __restrict__ state,
+                                                     int32_t* __restrict__ band_id) {
+    const int ql = blockIdx.y;
+    SelState* st = state + ql;
+    if (st->need_band_pass != 1) return;
+    const double tau = st->tau;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int64_t d0 = (int64_t)blockIdx.x * per_block, d1 = min(N, d0 + per_block);
+    const uint32_t* Sq = S + (int64_t)ql * ld;
+    int32_t* B = band_id + (int64_t)ql * kCandCap;
+    for (int64_t wb = d0 + wave * kWave; wb < d1; wb += 512) {
+        const int64_t d = wb + lane;
+        const bool take = d < d1 && (double)__uint_as_float(Sq[d]) >= tau;
+        const unsigned long long m = __ballot(take);
+        if (m == 0) continue;
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(&st->band, __popcll(m));
+        slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
+        if (take) {
+            if (slot < kCandCap) B[slot] = (int32_t)d;
+            else st->overflow = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_band_final(DevIndex ix, DevBatch qb, int32_t q0, SelState* __restrict__ state,
+                                                     double* __restrict__ band_s, int32_t* __restrict__ band_id,
+                                                     int32_t* __restrict__ out_ids, double* __restrict__ out_scores) {
+    __shared__ int32_t sq_t[kMaxQueryNnz];
+    __shared__ float sq_w[kMaxQueryNnz];
+    const int ql = blockIdx.x, q = q0 + ql;
+    SelState* st = state + ql;
+    if (st->need_band_pass != 1) return;
+    const int tid = threadIdx.x;
+    const int64_t qa = qb.q_row_ptr[q];
+    const int nq = (int)(qb.q_row_ptr[q + 1] - qa);
+    for (int i = tid; i < nq; i += 1024) {
+        sq_t[i] = qb.q_term[qa + i];
+        sq_w[i] = qb.q_w[qa + i];
+    }
+    __syncthreads();
+    const int nb = min(st->band, kCandCap);
+    double* bs = band_s + (int64_t)ql * kCandCap;
+    int32_t* bid = band_id + (int64_t)ql * kCandCap;
+    for (int i = tid; i < nb; i += 1024) bs[i] = rescore_f64(ix, bid[i], sq_t, sq_w, nq);
+    __threadfence_block();
+    __syncthreads();
+    const int64_t kq = kq_of(qb, q, ix.n_docs);
+    rank_band(bs, bid, nb, kq, out_ids + (int64_t)q * qb.k_max, out_scores + (int64_t)q * qb.k_max);
+}
+
+__global__ void k_diag(int32_t q0, int32_t qt, const SelState* __restrict__ state, int32_t* __restrict__ diag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= qt) return;
+    const SelState st = state[i];
+    int32_t* o = diag + (int64_t)(q0 + i) * 4;
+    o[0] = st.n_cand;
+    o[1] = st.passes;
+    o[2] = st.band;
+    o[3] = st.overflow;
+}
+
+}  // namespace
+
+hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const Workspace& ws,
+                         int32_t* out_ids, void* out_scores, int32_t* diag, hipStream_t s) {
+    const int64_t N = ix.n_docs;
+    const int per = 65536;
+    const dim3 grid_scan((unsigned)((N + per - 1) / per), (unsigned)qt);
+    hipLaunchKernelGGL(k_select_first, dim3(qt), dim3(64), 0, s, qb, q0, N, ix.precision,
+                       (const uint32_t*)ws.hist1, ws.state);
+    hipError_t e = hipGetLastError();
+    auto final_pass = [&]() {
+        switch (ix.precision) {
+            case kFP32:
+                hipLaunchKernelGGL(k_final<kFP32>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
+                                   (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores);
+                break;
+            case kU8:
+                hipLaunchKernelGGL(k_final<kU8>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
+                                   (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores);
+                break;
+            default:
+                hipLaunchKernelGGL(k_final<kBF16>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
+                                   (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores);
+                break;
+        }
+        return hipGetLastError();
+    };
+    if (N == 0) return e == hipSuccess ? final_pass() : e;  // empty collection: padding only
+    for (int p = 0; p < kRefinePasses && e == hipSuccess; p++) {
+        hipLaunchKernelGGL(k_refine_hist, grid_scan, dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores, ws.ld, per,
+                           (const SelState*)ws.state, ws.hist_ref);
+        hipLaunchKernelGGL(k_refine_select, dim3(qt), dim3(64), 0, s, qb, q0, N, ws.hist_ref, ws.state);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_filter, grid_scan, dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores, ws.ld, per, ws.state,
+                       ws.cand);
+    if ((e = final_pass()) != hipSuccess) return e;
+    if (ix.precision == kBF16) {
+        hipLaunchKernelGGL(k_band_filter, grid_scan, dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores, ws.ld, per,
+                           ws.state, ws.band_id);
+        hipLaunchKernelGGL(k_band_final, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state, ws.band_s, ws.band_id,
+                           out_ids, (double*)out_scores);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (diag) {
+        hipLaunchKernelGGL(k_diag, dim3((qt + 255) / 256), dim3(256), 0, s, q0, qt, (const SelState*)ws.state, diag);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace gs

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element by element.
+
+Sizes: the 10K-doc workload and synthetic instances spanning several doc tiles
+with a ragged tail, the 1M-doc workload on a query subset, and edge cases
+(empty query, k > N, k = 0, longest queries, exact ties, queries matching fewer
+than k documents).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from helpers import csr, dyadic, random_rows
+from parity_rules import check_batch, check_exact_f64, check_exact_int
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KERNELS = ["tiled", "atomic", "docpar"]
+
+
+def _gs():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    import paper_2606_26441_amd as gs
+    return gs
+
+
+def _run(gs, docs, queries, k, precision, kernel="tiled", tile_docs=0, chunk=0, query_tile=0, k_max=None):
+    idx = gs.Index.from_rows(docs, precision, keep_forward=(kernel == "docpar"))
+    b = idx.batch(queries, k, k_max)
+    opts = gs.make_opts(kernel, query_tile=query_tile, tile_docs=tile_docs, chunk=chunk)
+    ws = idx.workspace(max(1, min(queries.n_rows, 64)), opts)
+    ids, sc = idx.search(b, ws, opts)
+    import torch
+    torch.cuda.synchronize()
+    diag = b.diagnostics()
+    assert np.all(diag[:, 3] == 0), "candidate overflow"
+    return ids.cpu().numpy(), sc.cpu().numpy(), diag
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = workload.WORKLOADS["tiny-10k"]
+    return workload.make_collection(w), workload.make_queries(w)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "u8"])
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("k", [10, 100])
+def test_tiny_workload(tiny, precision, kernel, k):
+    gs = _gs()
+    docs, qs = tiny
+    ids, sc, _ = _run(gs, docs, qs, k, precision, kernel)
+    check_batch(precision, docs, qs, ids, sc, k, what="tiny %s %s k%d" % (precision, kernel, k))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "u8"])
+def test_hand_worked_example(precision):
+    gs = _gs()
+    g = json.load(open(os.path.join(GOLDEN, "tiny_example.json")))
+    docs, qs = csr(g["docs"], g["vocab"]), csr(g["queries"], g["vocab"])
+    for kernel in KERNELS:
+        ids, sc, _ = _run(gs, docs, qs, g["k"], precision, kernel)
+        exp = g["expected_i64"] if precision == "u8" else g["expected_f64"]
+        ok_ids = ids.tolist() == exp["ids"]
+        ok_sc = np.array_equal(sc.astype(np.float64), np.asarray(exp["scores"], np.float64))
+        assert ok_ids and ok_sc, kernel
+
+
+@pytest.mark.parametrize("tile_docs", [8192, 16384, 32768])
+@pytest.mark.parametrize("chunk", [64, 256, 1024])
+def test_dyadic_weights_are_bit_exact_across_tiles(tile_docs, chunk):
+    # multiples of 1/16: every fp32 partial sum is exact in any order, so fp32 must equal fp64 exactly
+    gs = _gs()
+    rng = np.random.default_rng(tile_docs + chunk)
+    docs = random_rows(rng, 41_000, 300, 1, 25, weight_fn=dyadic)
+    qs = random_rows(rng, 12, 300, 1, 40, weight_fn=dyadic)
+    rid, rsc = oracle.topk_f64(docs, qs, 300)
+    for kernel in ("tiled", "atomic"):
+        ids, sc, _ = _run(gs, docs, qs, 300, "fp32", kernel, tile_docs=tile_docs, chunk=chunk)
+        for q in range(qs.n_rows):
+            check_exact_f64(ids[q], sc[q], rid[q], rsc[q], "%s q%d" % (kernel, q))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "u8", "bf16"])
+def test_all_ones_weights_massive_ties(precision):
+    # scores are shared-term counts: thousands of exact ties at the k-th score, decided by doc id
+    gs = _gs()
+    rng = np.random.default_rng(5)
+    docs = random_rows(rng, 30_000, 40, 1, 10, weight_fn=lambda r, n: np.ones(n))
+    qs = random_rows(rng, 6, 40, 1, 8, weight_fn=lambda r, n: np.ones(n))
+    for kernel in KERNELS:
+        ids, sc, diag = _run(gs, docs, qs, 1000, precision, kernel)
+        check_batch(precision, docs, qs, ids, sc, 1000, what="ones %s" % kernel)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "u8"])
+def test_edge_cases(precision):
+    gs = _gs()
+    rng = np.random.default_rng(11)
+    V = 30522
+    docs = workload.collection(20_000, seed=99)
+    long_q = [(int(t), float(w)) for t, w in zip(np.sort(rng.choice(V, 256, replace=False)),
+                                                 np.log1p(rng.lognormal(0, 0.8, 256)))]
+    rare = int(np.argmin(np.where(np.bincount(docs.terms, minlength=V) > 0,
+                                  np.bincount(docs.terms, minlength=V), 1 << 30)))
+    rows = [
+        [],                        # empty query: all scores 0, ids ascending
+        long_q,                    # the longest allowed query
+        [(rare, 1.0)],             # matches very few docs: the answer is filled by doc id
+        [(int(docs.terms[0]), 2.0), (int(docs.terms[1]), 0.5)],
+    ]
+    qs = csr(rows, V)
+    k = np.array([7, 1000, 1000, 0], np.int32)
+    for kernel in KERNELS:
+        ids, sc, diag = _run(gs, docs, qs, k, precision, kernel, k_max=1000)
+        check_batch(precision, docs, qs, ids, sc, k, what="edge %s" % kernel)
+        assert np.all(ids[3] == -1)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "u8"])
+def test_k_beyond_collection_and_tiny_collections(precision):
+    gs = _gs()
+    rng = np.random.default_rng(12)
+    for n in (1, 5, 63, 64, 65, 3000):
+        docs = random_rows(rng, n, 20, 1, 6)
+        qs = random_rows(rng, 3, 20, 1, 5)
+        for kernel in KERNELS:
+            ids, sc, _ = _run(gs, docs, qs, [n + 3, max(1, n // 2), n], precision, kernel, k_max=n + 3)
+            check_batch(precision, docs, qs, ids, sc, [n + 3, max(1, n // 2), n], what="n%d %s" % (n, kernel))
+
+
+def test_query_tiling_matches_one_tile(tiny):
+    gs = _gs()
+    docs, qs = tiny
+    a, sa, _ = _run(gs, docs, qs, 100, "u8", "tiled", query_tile=3)
+    b, sb, _ = _run(gs, docs, qs, 100, "u8", "tiled", query_tile=0)
+    same = np.array_equal(a, b) and np.array_equal(sa, sb)
+    assert same
+
+
+def test_host_csr_entry_point_matches_prepared_batch(tiny):
+    # integer path: accumulation is order-independent, so two runs must agree bit for bit
+    gs = _gs()
+    docs, qs = tiny
+    idx = gs.Index.from_rows(docs, "u8")
+    ids, sc = idx.search_host(qs, 100)
+    ids2, sc2 = idx.search(idx.batch(qs, 100))
+    same = np.array_equal(ids.cpu().numpy(), ids2.cpu().numpy()) and np.array_equal(sc.cpu().numpy(),
+                                                                                     sc2.cpu().numpy())
+    assert same
+
+
+def test_search_errors_are_reported():
+    gs = _gs()
+    import torch
+    docs = random_rows(np.random.default_rng(1), 100, 20, 1, 5)
+    idx = gs.Index.from_rows(docs, "fp32")
+    qs = csr([[(1, 1.0)]], 20)
+    b = idx.batch(qs, 5)
+    tiny_ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gs.GsError) as e:
+        idx.search(b, tiny_ws)
+    assert e.value.code == gs.GS_ECAPACITY
+    with pytest.raises(gs.GsError) as e:
+        idx.search(b, opts=gs.make_opts("docpar"))
+    assert e.value.code == gs.GS_EUNSUPPORTED
+    with pytest.raises(gs.GsError):
+        idx.batch(csr([[(1, 1.0), (1, 2.0)]], 20), 5)
+    with pytest.raises(gs.GsError):
+        idx.batch(qs, [gs.GS_MAX_K + 1])
+
+
+@pytest.fixture(scope="module")
+def mid():
+    w = workload.WORKLOADS["mid-1m"]
+    return workload.make_collection(w), workload.make_queries(w, n=48)
+
+
+@pytest.mark.parametrize("precision,kernel", [("fp32", "tiled"), ("fp32", "atomic"), ("fp32", "docpar"),
+                                              ("u8", "tiled"), ("bf16", "tiled")])
+def test_mid_scale_top1000(mid, precision, kernel):
+    gs = _gs()
+    docs, qs = mid
+    ids, sc, diag = _run(gs, docs, qs, 1000, precision, kernel)
+    check_batch(precision, docs, qs, ids, sc, 1000, what="1M %s %s" % (precision, kernel))
