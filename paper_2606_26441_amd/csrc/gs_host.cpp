@@ -286,6 +286,7 @@ struct gs_index_s {
     int32_t vocab = 0, precision = 0;
     uint32_t flags = 0;
     size_t bytes = 0;
+    std::vector<float> term_max;  // largest stored weight of each term (value of the stored form)
     std::vector<void*> allocs;
     DevIndex dev{};
     ~gs_index_s() {
@@ -497,6 +498,10 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     ix->precision = precision;
     if (precision == kBF16) flags |= GS_KEEP_FORWARD;
     ix->flags = flags;
+    ix->term_max.assign((size_t)vocab_size, 0.0f);
+    for (int32_t v = 0; v < vocab_size; v++)
+        for (int64_t k = L.term_off[(size_t)v] / kBlock; k < L.term_off[(size_t)v + 1] / kBlock; k++)
+            ix->term_max[(size_t)v] = std::max(ix->term_max[(size_t)v], L.blk_max[(size_t)k]);
     DevIndex& d = ix->dev;
     d.n_docs = n_docs;
     d.vocab = vocab_size;
@@ -601,14 +606,18 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
     };
     std::vector<int64_t> rp(q_row_ptr ? q_row_ptr : nullptr, q_row_ptr ? q_row_ptr + n_queries + 1 : nullptr);
     if (rp.empty()) rp.push_back(0);
-    std::vector<int32_t> w8((size_t)q_nnz), fshift((size_t)n_queries);
+    std::vector<int32_t> w8((size_t)q_nnz), fshift((size_t)n_queries), qsh((size_t)q_nnz);
+    std::vector<uint32_t> qm((size_t)q_nnz);
     std::vector<float> delta((size_t)n_queries);
+    std::vector<double> qscale((size_t)n_queries), qerr((size_t)n_queries);
     for (int32_t q = 0; q < n_queries; q++) {
         uint64_t maxs = 0;
+        double maxscore = 0.0;
         const int64_t m = rp[(size_t)q + 1] - rp[(size_t)q];
         for (int64_t j = rp[(size_t)q]; j < rp[(size_t)q + 1]; j++) {
             w8[(size_t)j] = q8(r.w[j]);
             maxs += (uint64_t)w8[(size_t)j] * 255u;
+            maxscore += (double)r.w[j] * (double)ix->term_max[(size_t)r.term[j]];
         }
         if (ix->precision == kU8) {
             int hb = 0;
@@ -617,10 +626,21 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
         } else {
             fshift[(size_t)q] = kFirstShiftFloat;
         }
-        // |approx - exact| <= delta * exact for bf16 weights with fp32 products and sums of m terms
-        const double u = std::ldexp(1.0, -24);
-        const double gm = (double)(m + 1) * u / (1.0 - (double)(m + 1) * u);
-        delta[(size_t)q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + gm) - 1.0) * (1.0 + 1e-6));
+        // fixed point: units of 2^-F with every sum of this query's products below 2^62
+        int ex = 0;
+        if (maxscore > 0.0) (void)std::frexp(maxscore * (1.0 + 1e-9), &ex);  // maxscore < 2^ex
+        const int F = std::min(960, std::max(-60, 62 - ex));
+        qscale[(size_t)q] = std::ldexp(1.0, -F);
+        qerr[(size_t)q] = (double)(m + 1) * std::ldexp(1.0, -F) * (1.0 + 1e-6);  // products round up
+        for (int64_t j = rp[(size_t)q]; j < rp[(size_t)q + 1]; j++) {
+            uint32_t bits;
+            std::memcpy(&bits, &r.w[j], 4);
+            const uint32_t ef = (bits >> 23) & 0xffu;
+            qm[(size_t)j] = (bits & 0x7fffffu) | (ef ? 0x800000u : 0u);
+            qsh[(size_t)j] = (int32_t)(ef ? ef : 1u) - 300 + F;
+        }
+        // bf16 form: relative error of a stored weight (2^-8) and of the fp32 score (2^-24, with margin)
+        delta[(size_t)q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -23)) - 1.0) * (1.0 + 1e-6));
     }
     int64_t* d_rp = nullptr;
     int32_t *d_t = nullptr, *d_w8 = nullptr, *d_k = nullptr, *d_fs = nullptr;
@@ -633,6 +653,13 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
     if ((rc = dev_upload(b->allocs, bytes, k, (size_t)n_queries, &d_k, s))) return done(rc);
     if ((rc = dev_upload(b->allocs, bytes, fshift.data(), fshift.size(), &d_fs, s))) return done(rc);
     if ((rc = dev_upload(b->allocs, bytes, delta.data(), delta.size(), &d_delta, s))) return done(rc);
+    uint32_t* d_qm = nullptr;
+    int32_t* d_qsh = nullptr;
+    double *d_qscale = nullptr, *d_qerr = nullptr;
+    if ((rc = dev_upload(b->allocs, bytes, qm.data(), qm.size(), &d_qm, s))) return done(rc);
+    if ((rc = dev_upload(b->allocs, bytes, qsh.data(), qsh.size(), &d_qsh, s))) return done(rc);
+    if ((rc = dev_upload(b->allocs, bytes, qscale.data(), qscale.size(), &d_qscale, s))) return done(rc);
+    if ((rc = dev_upload(b->allocs, bytes, qerr.data(), qerr.size(), &d_qerr, s))) return done(rc);
     if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, (size_t)n_queries * 4, &b->diag, s))) return done(rc);
     hipError_t e = hipMemsetAsync(b->diag, 0, (size_t)std::max(n_queries, 1) * 16, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -647,6 +674,10 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
     d.k = d_k;
     d.first_shift = d_fs;
     d.delta = d_delta;
+    d.q_m = d_qm;
+    d.q_sh = d_qsh;
+    d.q_scale = d_qscale;
+    d.q_abs_err = d_qerr;
     *out = b;
     return GS_OK;
 }
@@ -659,7 +690,8 @@ void gs_batch_free(gs_batch b) {
 
 static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so) {
     so->kernel = GS_KERNEL_TILED;
-    so->tile_shift = 14;
+    // 64 KiB of LDS accumulators: 8192 fixed-point (fp32, bf16) or 16384 int32 (uint8) documents
+    so->tile_shift = ix->precision == kU8 ? 14 : 13;
     so->chunk = 256;
     so->group = 4;
     if (!o) return GS_OK;
@@ -678,6 +710,8 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
         case 32768: so->tile_shift = 15; break;
         default: return fail(GS_EINVAL, "tile_docs must be 0, 8192, 16384 or 32768");
     }
+    if (so->tile_shift == 15 && ix->precision != kU8)
+        return fail(GS_EUNSUPPORTED, "tile_docs 32768 is available for GS_U8 only (LDS capacity)");
     switch (o->chunk) {
         case 0: break;
         case 64: case 128: case 256: case 512: case 1024: so->chunk = o->chunk; break;

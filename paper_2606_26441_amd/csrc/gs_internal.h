@@ -47,6 +47,13 @@ struct DevBatch {
     const int32_t* k;          // [n]
     const int32_t* first_shift;  // [n] position of the first selection digit in the composite key
     const float* delta;        // [n] bf16 relative error bound per query (GS_BF16), else null
+    // fixed-point accumulation (GS_FP32, GS_BF16): a product w_q * w_d is formed exactly from the
+    // integer significands, m_q * m_d * 2^(q_sh + e_d), and summed as an unsigned 64-bit integer in
+    // units of 2^-F(q); F(q) is chosen per query so that no sum can reach 2^62.
+    const uint32_t* q_m;       // [q_nnz] significand of w_q (24 bits, hidden bit included)
+    const int32_t* q_sh;       // [q_nnz] exponent of w_q - 300 + F(q)
+    const double* q_scale;     // [n] 2^-F(q)
+    const double* q_abs_err;   // [n] bound on fixed-point sum - exact sum (>= 0: products round up)
 };
 
 // Per-query selection state in the workspace.

@@ -68,8 +68,6 @@ __device__ __forceinline__ unsigned long long comp_key(uint32_t key, uint32_t id
     return ((unsigned long long)key << 32) | (unsigned long long)(~id);
 }
 
-__device__ __forceinline__ void lds_add(uint32_t* a, float v) { atomicAdd(reinterpret_cast<float*>(a), v); }
-__device__ __forceinline__ void lds_add(uint32_t* a, int v) { atomicAdd(reinterpret_cast<int*>(a), v); }
 __device__ __forceinline__ void glb_add(uint32_t* a, float v) { unsafeAtomicAdd(reinterpret_cast<float*>(a), v); }
 __device__ __forceinline__ void glb_add(uint32_t* a, int v) { atomicAdd(reinterpret_cast<int*>(a), v); }
 
@@ -80,24 +78,56 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Write a finished LDS tile to the score array and add its first-digit
-// histogram (composite key (score bits, ~doc id), digit at first_shift).
-template <int BS>
-__device__ __forceinline__ void flush_tile(const uint32_t* acc, uint32_t* hist, int tile_n, int64_t base,
-                                           uint32_t* Sq, int fs, uint32_t* hist_out) {
+// Fixed-point product of a query weight (significand qm, shift qsh = e_q - 300 + F)
+// and a stored document weight given by its fp32 bit pattern (bf16 weights are
+// widened first): m_q * m_d * 2^(qsh + e_d) rounded UP to an integer, so a
+// product is zero exactly when w_q * w_d is zero and the sum never undershoots.
+// The per-query F guarantees that any sum of a query's products stays below 2^62.
+__device__ __forceinline__ unsigned long long fx_product(uint32_t qm, int qsh, uint32_t wbits) {
+    const uint32_t ef = (wbits >> 23) & 0xffu;
+    const uint32_t md = (wbits & 0x7fffffu) | (ef ? 0x800000u : 0u);
+    const int sh = qsh + (int)(ef ? ef : 1u);
+    const unsigned long long M = (unsigned long long)qm * md;
+    const int sl = sh > 0 ? sh : 0;
+    const int sr = sh < 0 ? (-sh < 62 ? -sh : 62) : 0;
+    const unsigned long long left = M << sl;
+    const unsigned long long right = (M + ((1ull << sr) - 1ull)) >> sr;
+    return sh >= 0 ? left : (-sh > 62 ? (M != 0ull ? 1ull : 0ull) : right);
+}
+
+__device__ __forceinline__ uint32_t stored_bits(const void* p, int64_t i, std::integral_constant<int, kFP32>) {
+    return ((const uint32_t*)p)[i];
+}
+__device__ __forceinline__ uint32_t stored_bits(const void* p, int64_t i, std::integral_constant<int, kBF16>) {
+    return (uint32_t)((const uint16_t*)p)[i] << 16;
+}
+
+// Write a finished LDS tile to the score array (fp32 bits or int32) and add its
+// first-digit histogram (composite key (score bits, ~doc id), digit at fs).
+template <int BS, bool FX>
+__device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, int tile_n, int64_t base, uint32_t* Sq,
+                                           int fs, double scale, uint32_t* hist_out) {
     const int tid = threadIdx.x;
     const int n4 = tile_n >> 2;
     for (int i = tid; i < n4; i += BS) {
-        uint4 v = reinterpret_cast<const uint4*>(acc)[i];
-        reinterpret_cast<uint4*>(Sq)[i] = v;
+        uint32_t v[4];
+        if constexpr (FX) {
+            const unsigned long long* acc = (const unsigned long long*)acc_v;
+#pragma unroll
+            for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)acc[4 * i + j] * scale));
+        } else {
+            const uint4 u = reinterpret_cast<const uint4*>(acc_v)[i];
+            v[0] = u.x; v[1] = u.y; v[2] = u.z; v[3] = u.w;
+        }
+        reinterpret_cast<uint4*>(Sq)[i] = make_uint4(v[0], v[1], v[2], v[3]);
         const uint32_t d0 = (uint32_t)(base + 4 * i);
-        atomicAdd(&hist[(comp_key(v.x, d0 + 0) >> fs) & (kHistBins - 1)], 1u);
-        atomicAdd(&hist[(comp_key(v.y, d0 + 1) >> fs) & (kHistBins - 1)], 1u);
-        atomicAdd(&hist[(comp_key(v.z, d0 + 2) >> fs) & (kHistBins - 1)], 1u);
-        atomicAdd(&hist[(comp_key(v.w, d0 + 3) >> fs) & (kHistBins - 1)], 1u);
+#pragma unroll
+        for (int j = 0; j < 4; j++) atomicAdd(&hist[(comp_key(v[j], d0 + j) >> fs) & (kHistBins - 1)], 1u);
     }
     for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
-        uint32_t v = acc[i];
+        uint32_t v;
+        if constexpr (FX) v = __float_as_uint((float)((double)((const unsigned long long*)acc_v)[i] * scale));
+        else v = ((const uint32_t*)acc_v)[i];
         Sq[i] = v;
         atomicAdd(&hist[(comp_key(v, (uint32_t)(base + i)) >> fs) & (kHistBins - 1)], 1u);
     }
@@ -107,19 +137,29 @@ __device__ __forceinline__ void flush_tile(const uint32_t* acc, uint32_t* hist, 
 }
 
 // ------------------------------------------------------------- tiled --
+//
+// One workgroup per (query, doc tile of 2^TS docs). LDS holds the tile's
+// accumulators: unsigned 64-bit fixed point for fp32/bf16 weights (LDS integer
+// atomics run far faster than LDS float atomics on this GPU, and integer sums do
+// not depend on the order of the updates), int32 for uint8 impacts. Work inside
+// the workgroup: the query's posting segments for this tile are cut into chunks
+// of CH postings; wavefronts take chunks round-robin, each lane loads CH/64
+// postings (coalesced across the wavefront) before issuing its LDS adds.
 
 template <int P, int TS, int CH>
 __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
                                                      int64_t ld, uint32_t* __restrict__ hist1) {
     constexpr int BS = 512, NW = BS / kWave, TILE = 1 << TS, U = CH / kWave, GPT = TS - kGrainShift;
-    using Acc = typename WF<P>::Acc;
+    constexpr bool FX = P != kU8;
     extern __shared__ __align__(16) uint32_t lds[];
-    uint32_t* acc = lds;            // [TILE]
-    uint32_t* hist = lds + TILE;    // [kHistBins]
+    unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(lds);  // [TILE] (FX)
+    uint32_t* acc32 = lds;                                                   // [TILE] (uint8)
+    uint32_t* hist = lds + TILE * (FX ? 2 : 1);                               // [kHistBins]
     __shared__ int64_t seg_beg[kMaxQueryNnz];
     __shared__ int32_t seg_len[kMaxQueryNnz];
     __shared__ int32_t seg_cpre[kMaxQueryNnz + 1];
-    __shared__ Acc seg_w[kMaxQueryNnz];
+    __shared__ uint32_t seg_a[kMaxQueryNnz];  // q_m (fixed point) or the uint8 query impact
+    __shared__ int32_t seg_b[kMaxQueryNnz];   // q_sh (fixed point)
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const int ql = blockIdx.y, q = q0 + ql;
@@ -127,7 +167,7 @@ __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, i
     const int64_t base = (int64_t)blockIdx.x << TS;
     const int tile_n = (int)min((int64_t)TILE, N - base);
 
-    for (int i = tid; i < TILE; i += BS) acc[i] = 0u;
+    for (int i = tid; i < TILE * (FX ? 2 : 1); i += BS) lds[i] = 0u;
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
 
     const int64_t qa = qb.q_row_ptr[q];
@@ -140,7 +180,12 @@ __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, i
         const int a = row[g0], b = row[g1];
         seg_beg[t] = ix.term_off[term] + a;
         seg_len[t] = b - a;
-        seg_w[t] = WF<P>::qweight(qb, qa + t);
+        if constexpr (FX) {
+            seg_a[t] = qb.q_m[qa + t];
+            seg_b[t] = qb.q_sh[qa + t];
+        } else {
+            seg_a[t] = (uint32_t)qb.q_w8[qa + t];
+        }
     }
     __syncthreads();
     if (wave == 0) {
@@ -179,26 +224,32 @@ __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, i
         const int off = (c - seg_cpre[lo]) * CH;
         const int n = min(CH, seg_len[lo] - off);
         const int64_t p0 = seg_beg[lo] + off;
-        const Acc wq = seg_w[lo];
+        const uint32_t qa_ = seg_a[lo];
+        const int qb_ = seg_b[lo];
         int doc[U];
-        Acc w[U];
+        uint32_t wb[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int i = lane + u * kWave;
+            doc[u] = (int)base;
+            wb[u] = 0u;
             if (i < n) {
-                doc[u] = __builtin_nontemporal_load(ix.post_doc + p0 + i);
-                w[u] = WF<P>::load(ix.post_w, p0 + i);
+                doc[u] = ix.post_doc[p0 + i];
+                if constexpr (P == kU8) wb[u] = ((const uint8_t*)ix.post_w)[p0 + i];
+                else wb[u] = stored_bits(ix.post_w, p0 + i, std::integral_constant<int, P>());
             }
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int i = lane + u * kWave;
-            if (i < n) lds_add(&acc[doc[u] - base], wq * w[u]);
+            if (lane + u * kWave < n) {
+                if constexpr (FX) atomicAdd(&acc64[doc[u] - base], fx_product(qa_, qb_, wb[u]));
+                else atomicAdd(&acc32[doc[u] - base], qa_ * wb[u]);
+            }
         }
     }
     __syncthreads();
-    flush_tile<BS>(acc, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
-                   hist1 + (int64_t)ql * kHistBins);
+    flush_tile<BS, FX>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
+                       FX ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins);
 }
 
 // ------------------------------------------------------------ atomic --
@@ -353,7 +404,8 @@ template <int P, int TS>
 hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, const Workspace& ws,
                        int64_t ld, hipStream_t s) {
     const dim3 grid((unsigned)((ix.n_docs + (1 << TS) - 1) >> TS), (unsigned)qt);
-    const size_t lds = (size_t)((1 << TS) + kHistBins) * 4;
+    const size_t lds = (size_t)((1 << TS) * (P == kU8 ? 1 : 2) + kHistBins) * 4;
+    if (lds > 150 * 1024) return hipErrorInvalidValue;
     if (lds > 65536) {
         static const hipError_t attr = [&] {
             hipError_t e = hipSuccess;
@@ -396,7 +448,9 @@ hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0
         switch (o.tile_shift) {
             case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, ws, ld, s);
             case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, ws, ld, s);
-            case 15: return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, ws, ld, s);
+            case 15:
+                if constexpr (P == kU8) return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, ws, ld, s);
+                return hipErrorInvalidValue;  // 32768 fixed-point accumulators exceed one CU's LDS
         }
         return hipErrorInvalidValue;
     });

@@ -215,10 +215,16 @@ __device__ void rank_band(const double* bs, const int32_t* bid, int nb, int64_t 
     }
 }
 
-__device__ __forceinline__ double band_tau(float sk, float delta) {
-    // every true top-k doc has approx >= s_k*(1-delta) >= approx_k*(1-delta)/(1+delta)
+// Band of the bf16 form. Every doc's approximate score satisfies
+//   s(1-delta) <= approx <= s(1+delta) + E
+// (delta: relative error of the stored bf16 weights and of the fp32 score; E:
+// the fixed-point excess, products round up, so approx = 0 exactly when s = 0).
+// Then approx_k <= (1+delta) s_k + E, and every true top-k doc has
+//   approx >= s(1-delta) >= s_k(1-delta) >= (approx_k - E)(1-delta)/(1+delta) = tau.
+__device__ __forceinline__ double band_tau(float sk, float delta, double abs_err) {
     const double d = (double)delta;
-    return (double)sk * (1.0 - d) / (1.0 + d) * (1.0 - 1e-12);
+    const double t = ((double)sk - abs_err) * (1.0 - d) / (1.0 + d);
+    return t > 0.0 ? t * (1.0 - 1e-12) : 0.0;
 }
 
 template <int P>
@@ -337,10 +343,27 @@ __global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_
     }
     __syncthreads();
     const float sk = __uint_as_float((uint32_t)(sh_min >> 32));
-    const double tau = band_tau(sk, qb.delta[q]);
+    double* bs = band_s + (int64_t)ql * kCandCap;
+    int32_t* bid = band_id + (int64_t)ql * kCandCap;
+    if (sk == 0.0f) {
+        // fewer than k docs share a term with the query: the k winners are every doc with a
+        // positive score plus the lowest-id zero-score docs; zeros are exact, positives are rescored
+        for (int i = tid; i < m; i += 1024) {
+            const unsigned long long c = sel[i];
+            const int32_t doc = (int32_t)(~(uint32_t)c);
+            bid[i] = doc;
+            bs[i] = (c >> 32) ? rescore_f64(ix, doc, sq_t, sq_w, nq) : 0.0;
+        }
+        if (tid == 0) st->band = m;
+        __threadfence_block();
+        __syncthreads();
+        rank_band(bs, bid, m, kq, ids, (double*)out_scores + (int64_t)q * kmax);
+        return;
+    }
+    const double tau = band_tau(sk, qb.delta[q], qb.q_abs_err[q]);
     const unsigned long long lo = st->lo;
     const double lo_val = (double)__uint_as_float((uint32_t)(lo >> 32));
-    const bool inside = ((uint32_t)lo == 0u) ? (lo_val <= tau) : (lo_val < tau);
+    const bool inside = tau > 0.0 && (((uint32_t)lo == 0u) ? (lo_val <= tau) : (lo_val < tau));
     if (!inside) {
         if (tid == 0) {
             st->need_band_pass = 1;
@@ -348,13 +371,12 @@ __global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_
         }
         return;
     }
-    double* bs = band_s + (int64_t)ql * kCandCap;
-    int32_t* bid = band_id + (int64_t)ql * kCandCap;
     if (tid == 0) sh_cnt = 0;
     __syncthreads();
     for (int i = tid; i < n; i += 1024) {
         const unsigned long long c = C[i];
-        if ((double)__uint_as_float((uint32_t)(c >> 32)) >= tau) {
+        const double v = (double)__uint_as_float((uint32_t)(c >> 32));
+        if (v > 0.0 && v >= tau) {
             const int pos = atomicAdd(&sh_cnt, 1);
             const int32_t doc = (int32_t)(~(uint32_t)c);
             bid[pos] = doc;
@@ -382,7 +404,8 @@ __global__ __launch_bounds__(512) void k_band_filter(int32_t q0, int64_t N, cons
     int32_t* B = band_id + (int64_t)ql * kCandCap;
     for (int64_t wb = d0 + wave * kWave; wb < d1; wb += 512) {
         const int64_t d = wb + lane;
-        const bool take = d < d1 && (double)__uint_as_float(Sq[d]) >= tau;
+        const double v = d < d1 ? (double)__uint_as_float(Sq[d]) : 0.0;
+        const bool take = v > 0.0 && v >= tau;
         const unsigned long long m = __ballot(take);
         if (m == 0) continue;
         int slot = 0;

@@ -71,19 +71,36 @@ def test_hand_worked_example(precision):
         assert ok_ids and ok_sc, kernel
 
 
-@pytest.mark.parametrize("tile_docs", [8192, 16384, 32768])
+@pytest.mark.parametrize("precision,tile_docs", [("fp32", 8192), ("fp32", 16384), ("u8", 8192), ("u8", 16384),
+                                                 ("u8", 32768), ("bf16", 8192)])
 @pytest.mark.parametrize("chunk", [64, 256, 1024])
-def test_dyadic_weights_are_bit_exact_across_tiles(tile_docs, chunk):
-    # multiples of 1/16: every fp32 partial sum is exact in any order, so fp32 must equal fp64 exactly
+def test_dyadic_weights_are_exact_across_tiles(precision, tile_docs, chunk):
+    # multiples of 1/16: every sum is exact, so fp32 scores must equal the fp64 oracle bit for bit
     gs = _gs()
     rng = np.random.default_rng(tile_docs + chunk)
     docs = random_rows(rng, 41_000, 300, 1, 25, weight_fn=dyadic)
     qs = random_rows(rng, 12, 300, 1, 40, weight_fn=dyadic)
-    rid, rsc = oracle.topk_f64(docs, qs, 300)
-    for kernel in ("tiled", "atomic"):
-        ids, sc, _ = _run(gs, docs, qs, 300, "fp32", kernel, tile_docs=tile_docs, chunk=chunk)
+    if precision == "u8":
+        rid, rsc = oracle.topk_i64(docs, qs, 300)
+    else:
+        rid, rsc = oracle.topk_f64(docs, qs, 300)
+    kernels = ("tiled", "atomic") if precision == "fp32" else ("tiled",)
+    for kernel in kernels:
+        ids, sc, _ = _run(gs, docs, qs, 300, precision, kernel, tile_docs=tile_docs, chunk=chunk)
         for q in range(qs.n_rows):
-            check_exact_f64(ids[q], sc[q], rid[q], rsc[q], "%s q%d" % (kernel, q))
+            if precision == "u8":
+                check_exact_int(ids[q], sc[q], rid[q], rsc[q], "%s q%d" % (kernel, q))
+            else:
+                check_exact_f64(ids[q], sc[q], rid[q], rsc[q], "%s q%d" % (kernel, q))
+
+
+def test_fixed_point_tiles_reject_32768_docs():
+    gs = _gs()
+    docs = random_rows(np.random.default_rng(2), 100, 20, 1, 5)
+    idx = gs.Index.from_rows(docs, "fp32")
+    with pytest.raises(gs.GsError) as e:
+        idx.workspace_bytes(1, gs.make_opts("tiled", tile_docs=32768))
+    assert e.value.code == gs.GS_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("precision", ["fp32", "u8", "bf16"])
