@@ -63,6 +63,25 @@ def algorithmic_bytes(df, queries, n_docs, wbytes):
     return p_q, score_kernel, step
 
 
+def profiled_traffic(kernel, precision, workload_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel source is unchanged."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        text = open(path).read()
+        if "```json" not in text:
+            continue
+        meta = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        if (meta.get("kernel"), meta.get("precision"), meta.get("workload")) != (kernel, precision, workload_name):
+            continue
+        h = hashlib.sha256()
+        for f in meta["source_files"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() == meta["source_sha256"]:
+            return int(meta["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
+
+
 def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_forward=False):
     idx = gs.Index.from_rows(docs, precision, keep_forward=keep_forward)
     batch = idx.batch(queries, k)
@@ -116,6 +135,22 @@ def main():
     df = np.bincount(docs.terms, minlength=docs.vocab)
     opts = gs.make_opts(args.kernel, tile_docs=args.tile_docs, chunk=args.chunk)
 
+    # yardstick: a plain 2 GiB device copy (reads and writes exactly its size once)
+    src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    gs.device_copy(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        gs.device_copy(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    log("device copy yardstick: %.0f GB/s (read + write)" % copy_gbs)
+
     log("main form: %s / %s, %d warmup + %d timed steps" % (args.precision, args.kernel, args.warmup, args.steps))
     main_res = time_form(gs, torch, docs, queries, args.k, args.precision, opts, args.steps, args.warmup,
                          keep_forward=(args.kernel == "docpar"))
@@ -129,6 +164,9 @@ def main():
     log("QPS %.1f  ms/step %.2f  score %.2f ms  select %.2f ms  score kernel %.0f GB/s"
         % (qps, ms_per_step, score_ms, select_ms, achieved))
 
+    traffic, traffic_src = (None, None)
+    if args.kernel == "tiled" and args.n_docs in (0, w.n_docs) and nq == w.n_queries:
+        traffic, traffic_src = profiled_traffic("k_score_tiled", args.precision, w.name)
     out = {
         "metric": METRIC,
         "value": round(qps, 2),
@@ -143,12 +181,13 @@ def main():
         "dtype": DTYPE[args.precision],
         "data": "synthetic (seeded Zipf(1.1)/Poisson/lognormal stand-in for MS MARCO + SPLADE)",
         "config": {"workload": w.name, "n_docs": n_docs, "postings": docs.nnz, "batch": nq, "k": args.k,
-                   "precision": args.precision, "kernel": args.kernel, "tile_docs": args.tile_docs or 16384,
+                   "precision": args.precision, "kernel": args.kernel, "tile_docs": args.tile_docs or (16384 if args.precision == "u8" else 8192),
                    "chunk": args.chunk or 256, "query_nnz_mean": round(queries.nnz / max(nq, 1), 2),
                    "postings_per_query_mean": int(p_q.mean())},
         "roofline": {"bound": "hbm", "kernel": "k_score_tiled" if args.kernel == "tiled" else "score_" + args.kernel,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "algorithmic_bytes_per_launch": score_bytes, "launch_ms": round(score_ms, 4),
                      "queries_per_launch": nq},
         "step": {"p50_ms": round(float(np.percentile(main_res["step_ms"], 50)), 3),
@@ -156,6 +195,7 @@ def main():
                  "score_ms": round(score_ms, 3), "select_ms": round(select_ms, 3),
                  "hbm_frac_whole_step": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "memory": {"index_bytes": main_res["device_bytes"], "workspace_bytes": main_res["ws_bytes"]},
+        "hbm_copy_GBs": round(copy_gbs, 1),
         "selection": {"candidates_mean": float(main_res["diag"][:, 0].mean()),
                       "refine_passes_max": int(main_res["diag"][:, 1].max()),
                       "overflow": int(main_res["diag"][:, 3].max())},

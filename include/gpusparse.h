@@ -233,6 +233,14 @@ int32_t gs_timing_enable(int32_t on);
 int32_t gs_timing_read(double* score_ms, int64_t* score_launches, double* select_ms,
                        int64_t* select_launches);
 
+/*
+ * Plain device-to-device copy of `bytes` (a multiple of 16; both pointers
+ * 16-byte aligned) with 16-byte vector loads and stores: the yardstick that
+ * hardware traffic counters are calibrated against (it moves exactly `bytes`
+ * in each direction). Asynchronous. Errors: GS_EINVAL, GS_EHIP.
+ */
+int32_t gs_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,8 @@ def _load() -> ctypes.CDLL:
     lib.gs_search.restype = i32
     lib.gs_batch_diagnostics.argtypes = [vp, vp]
     lib.gs_batch_diagnostics.restype = i32
+    lib.gs_device_copy.argtypes = [vp, vp, sz, vp]
+    lib.gs_device_copy.restype = i32
     lib.gs_timing_enable.argtypes = [i32]
     lib.gs_timing_enable.restype = i32
     lib.gs_timing_read.argtypes = [P(ctypes.c_double), P(i64), P(ctypes.c_double), P(i64)]
@@ -261,6 +263,12 @@ class Batch:
 
 def version() -> str:
     return lib.gs_version().decode()
+
+
+def device_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    """Plain 16-byte-vector copy (traffic-counter yardstick)."""
+    n = min(dst.numel() * dst.element_size(), src.numel() * src.element_size())
+    _check(lib.gs_device_copy(dst.data_ptr(), src.data_ptr(), n, _stream_ptr(stream)), "gs_device_copy")
 
 
 def timing_enable(on: bool = True):

@@ -832,6 +832,14 @@ int32_t gs_timing_read(double* score_ms, int64_t* score_launches, double* select
     return GS_OK;
 }
 
+int32_t gs_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+    g_err.clear();
+    if (!dst || !src) return fail(GS_EINVAL, "null pointer");
+    if (bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) return fail(GS_EINVAL, "copy needs 16-byte sizes and alignment");
+    GS_HIP(launch_copy16(dst, src, (int64_t)(bytes / 16), (hipStream_t)hip_stream));
+    return GS_OK;
+}
+
 int32_t gs_batch_diagnostics(gs_batch b, int32_t* out) {
     g_err.clear();
     if (!b || !out) return fail(GS_EINVAL, "null argument");

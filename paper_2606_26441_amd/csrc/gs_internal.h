@@ -105,6 +105,7 @@ hipError_t launch_score_docpar(const DevIndex& ix, const DevBatch& qb, int32_t q
                                const ScoreOpts& o, const Workspace& ws, hipStream_t s);
 hipError_t launch_hist1(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                         const Workspace& ws, hipStream_t s);
+hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s);
 
 // ---- launchers (gs_topk.hip) ----
 hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,

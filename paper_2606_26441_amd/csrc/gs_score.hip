@@ -383,6 +383,11 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
+__global__ __launch_bounds__(256) void k_copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 hipError_t fill_u32(void* p, int64_t n_words, hipStream_t s) {
     if (n_words <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((n_words + 255) / 256, 8192);
@@ -432,6 +437,12 @@ hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32
 }  // namespace
 
 int64_t score_ld(int64_t n_docs) { return (n_docs + 63) / 64 * 64; }
+
+hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s) {
+    if (n16 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy16, dim3(4096), dim3(256), 0, s, (uint4*)dst, (const uint4*)src, n16);
+    return hipGetLastError();
+}
 
 hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s) {
     hipError_t e = fill_u32(ws.hist1, (int64_t)qt * kHistBins, s);
