@@ -46,10 +46,11 @@ def parse():
     ap.add_argument("--batch", type=int, default=0, help="override the number of queries")
     ap.add_argument("--k", type=int, default=1000)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "u8"])
-    ap.add_argument("--kernel", default="tiled", choices=["tiled", "atomic", "docpar"])
+    ap.add_argument("--kernel", default="tiled", choices=["tiled", "atomic", "docpar", "shared"])
     ap.add_argument("--tile-docs", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--forms", default="u8,bf16", help="other precisions to time (comma list, or 'none')")
+    ap.add_argument("--forms", default="u8,bf16,fp32:shared,u8:shared,bf16:shared",
+                    help="other precision[:kernel] forms to time (comma list, or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16, help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--profile", action="store_true", help="main form only, no CPU leg (for profiler runs)")
     return ap.parse_args()
@@ -203,18 +204,24 @@ def main():
 
     forms = {}
     if not args.profile and args.forms != "none":
-        for prec in [f for f in args.forms.split(",") if f and f != args.precision]:
-            log("form %s ..." % prec)
-            r = time_form(gs, torch, docs, queries, args.k, prec, opts, max(3, args.steps // 2), 1)
-            ms = r["total_ms"] / max(3, args.steps // 2)
+        for spec in [f for f in args.forms.split(",") if f]:
+            prec, _, kern = spec.partition(":")
+            kern = kern or "tiled"
+            if (prec, kern) == (args.precision, args.kernel):
+                continue
+            name = prec if kern == "tiled" else prec + ":" + kern
+            log("form %s ..." % name)
+            fsteps = max(3, args.steps // 2)
+            r = time_form(gs, torch, docs, queries, args.k, prec, gs.make_opts(kern), fsteps, 1)
+            ms = r["total_ms"] / fsteps
             t = r["timing"]
-            forms[prec] = {"qps": round(nq / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
+            forms[name] = {"qps": round(nq / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
                            "score_ms": round(t["score_ms"] / max(t["score_launches"], 1), 3),
                            "select_ms": round(t["select_ms"] / max(t["select_launches"], 1), 3),
                            "index_bytes": r["device_bytes"],
                            "overflow": int(r["diag"][:, 3].max())}
-            forms[prec]["_res"] = r
-            log("form %s: QPS %.1f" % (prec, forms[prec]["qps"]))
+            forms[name]["_res"] = r
+            log("form %s: QPS %.1f" % (name, forms[name]["qps"]))
 
     if not args.profile and args.cpu_sample > 0:
         import oracle
@@ -234,24 +241,27 @@ def main():
                                          "with full sort; %.1f s wall" % (s, nq, n_docs, args.k, cpu_s)}
         # full-size parity of the timed launch configuration on the same sample
         checked = {}
+        rid8 = rsc8 = None
+        s8 = min(4, s)
         try:
-            for q in range(s):
-                t_, w_ = queries.row(q)
-                if args.precision == "fp32":
-                    check_fp32(docs, t_, w_, main_res["ids"][q], main_res["scores"][q], rid[q], rsc[q], args.k)
-            checked[args.precision] = "ok (%d queries)" % s
-            if "bf16" in forms:
-                r = forms["bf16"]["_res"]
-                for q in range(s):
-                    check_exact_f64(r["ids"][q], r["scores"][q], rid[q], rsc[q])
-                checked["bf16"] = "ids and fp64 scores identical (%d queries)" % s
-            if "u8" in forms:
-                s8 = min(4, s)
-                rid8, rsc8 = oracle.topk_i64(docs, queries.subset(np.arange(s8)), args.k, n_threads=threads)
-                r = forms["u8"]["_res"]
-                for q in range(s8):
-                    check_exact_int(r["ids"][q], r["scores"][q], rid8[q], rsc8[q])
-                checked["u8"] = "bit-exact (%d queries)" % s8
+            for name, res in [(args.precision if args.kernel == "tiled" else args.precision + ":" + args.kernel,
+                               main_res)] + [(n, f["_res"]) for n, f in forms.items()]:
+                prec = name.split(":")[0]
+                if prec == "fp32":
+                    for q in range(s):
+                        t_, w_ = queries.row(q)
+                        check_fp32(docs, t_, w_, res["ids"][q], res["scores"][q], rid[q], rsc[q], args.k, what=name)
+                    checked[name] = "within 1e-5, ids equal up to tolerance swaps (%d queries)" % s
+                elif prec == "bf16":
+                    for q in range(s):
+                        check_exact_f64(res["ids"][q], res["scores"][q], rid[q], rsc[q], what=name)
+                    checked[name] = "ids and fp64 scores identical (%d queries)" % s
+                else:
+                    if rid8 is None:
+                        rid8, rsc8 = oracle.topk_i64(docs, queries.subset(np.arange(s8)), args.k, n_threads=threads)
+                    for q in range(s8):
+                        check_exact_int(res["ids"][q], res["scores"][q], rid8[q], rsc8[q], what=name)
+                    checked[name] = "bit-exact (%d queries)" % s8
         except AssertionError as e:
             checked["error"] = str(e)[:200]
         out["parity_sample"] = checked

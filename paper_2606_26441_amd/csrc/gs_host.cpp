@@ -19,6 +19,10 @@
 
 using namespace gs;
 
+namespace gs {
+thread_local const char* g_failed_launch = "";
+}
+
 namespace {
 
 thread_local std::string g_err;
@@ -699,7 +703,6 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
         if (o->reserved[i] != 0) return fail(GS_EINVAL, "reserved option fields must be 0");
     if (o->kernel < GS_KERNEL_AUTO || o->kernel > GS_KERNEL_SHARED) return fail(GS_EINVAL, "unknown kernel");
     if (o->kernel != GS_KERNEL_AUTO) so->kernel = o->kernel;
-    if (so->kernel == GS_KERNEL_SHARED) return fail(GS_EUNSUPPORTED, "shared-traversal kernel not built yet");
     if (so->kernel == GS_KERNEL_DOCPAR && !(ix->flags & GS_KEEP_FORWARD))
         return fail(GS_EUNSUPPORTED, "document-parallel kernel needs an index built with GS_KEEP_FORWARD");
     if (o->query_tile < 0) return fail(GS_EINVAL, "query_tile < 0");
@@ -761,6 +764,8 @@ int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspa
     hipStream_t s = (hipStream_t)hip_stream;
     Workspace ws;
     carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
+    (void)hipGetLastError();  // launches below report their own status; drop any earlier, unrelated one
+    g_failed_launch = "";
     for (int32_t q0 = 0; q0 < nq; q0 += qt) {
         const int32_t n = std::min(qt, nq - q0);
         hipError_t e = launch_clear(ws, n, s);
@@ -776,7 +781,8 @@ int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspa
             e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s);
             rec.end(s);
         }
-        if (e != hipSuccess) return fail(GS_EHIP, std::string("launch: ") + hipGetErrorString(e));
+        if (e != hipSuccess)
+            return fail(GS_EHIP, std::string("launch of ") + g_failed_launch + ": " + hipGetErrorString(e));
     }
     return GS_OK;
 }
@@ -836,6 +842,7 @@ int32_t gs_device_copy(void* dst, const void* src, size_t bytes, void* hip_strea
     g_err.clear();
     if (!dst || !src) return fail(GS_EINVAL, "null pointer");
     if (bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) return fail(GS_EINVAL, "copy needs 16-byte sizes and alignment");
+    (void)hipGetLastError();
     GS_HIP(launch_copy16(dst, src, (int64_t)(bytes / 16), (hipStream_t)hip_stream));
     return GS_OK;
 }

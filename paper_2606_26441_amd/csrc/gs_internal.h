@@ -20,6 +20,18 @@ constexpr int kFirstShiftFloat = 52;  // first digit of a float key: bits 30..20
 
 enum Precision { kFP32 = 0, kBF16 = 1, kU8 = 2 };
 
+// Name of the kernel whose launch failed last on this thread (for error messages).
+extern thread_local const char* g_failed_launch;
+
+#define GS_CHECK_LAUNCH(name)                      \
+    do {                                           \
+        const hipError_t e_ = hipGetLastError();   \
+        if (e_ != hipSuccess) {                    \
+            ::gs::g_failed_launch = (name);        \
+            return e_;                             \
+        }                                          \
+    } while (0)
+
 // Index arrays on the device (plain pointers; passed by value to kernels).
 struct DevIndex {
     int64_t n_docs;

@@ -146,11 +146,35 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
 // of CH postings; wavefronts take chunks round-robin, each lane loads CH/64
 // postings (coalesced across the wavefront) before issuing its LDS adds.
 
+// Block order. Query-major (order 0): grid (tiles, queries), the tiles of one
+// query are consecutive, so every query streams its own postings from HBM.
+// Tile-major, XCD-aware (order 1): a 1-D grid in which workgroup b runs on XCD
+// b % 8 (round-robin dispatch); XCD x takes the tiles x, x+8, x+16, ... and runs
+// every query of the tile before the next tile, so a tile's posting segments are
+// fetched from HBM once and re-read by the other queries from that XCD's L2 and
+// the shared last-level cache (shared traversal of common terms).
+__device__ __forceinline__ bool block_coords(int order, int32_t qt, int64_t n_tiles, int64_t* tile, int* ql) {
+    if (order == 0) {
+        *tile = blockIdx.x;
+        *ql = (int)blockIdx.y;
+        return true;
+    }
+    const int64_t b = blockIdx.x;
+    const int64_t x = b & 7, r = b >> 3;
+    *tile = (r / qt) * 8 + x;
+    *ql = (int)(r % qt);
+    return *tile < n_tiles;
+}
+
 template <int P, int TS, int CH>
-__global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
-                                                     int64_t ld, uint32_t* __restrict__ hist1) {
+__global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, int32_t q0, int32_t qt, int order,
+                                                     uint32_t* __restrict__ S, int64_t ld,
+                                                     uint32_t* __restrict__ hist1) {
     constexpr int BS = 512, NW = BS / kWave, TILE = 1 << TS, U = CH / kWave, GPT = TS - kGrainShift;
     constexpr bool FX = P != kU8;
+    int64_t tile;
+    int ql;
+    if (!block_coords(order, qt, (ix.n_docs + TILE - 1) >> TS, &tile, &ql)) return;
     extern __shared__ __align__(16) uint32_t lds[];
     unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(lds);  // [TILE] (FX)
     uint32_t* acc32 = lds;                                                   // [TILE] (uint8)
@@ -162,9 +186,9 @@ __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, i
     __shared__ int32_t seg_b[kMaxQueryNnz];   // q_sh (fixed point)
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
-    const int ql = blockIdx.y, q = q0 + ql;
+    const int q = q0 + ql;
     const int64_t N = ix.n_docs;
-    const int64_t base = (int64_t)blockIdx.x << TS;
+    const int64_t base = tile << TS;
     const int tile_n = (int)min((int64_t)TILE, N - base);
 
     for (int i = tid; i < TILE * (FX ? 2 : 1); i += BS) lds[i] = 0u;
@@ -172,7 +196,7 @@ __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, i
 
     const int64_t qa = qb.q_row_ptr[q];
     const int nq = (int)(qb.q_row_ptr[q + 1] - qa);
-    const int64_t g0 = (int64_t)blockIdx.x << GPT;
+    const int64_t g0 = tile << GPT;
     const int64_t g1 = min(g0 + (int64_t)(1 << GPT), ix.n_grains);
     for (int t = tid; t < nq; t += BS) {
         const int term = qb.q_term[qa + t];
@@ -392,7 +416,8 @@ hipError_t fill_u32(void* p, int64_t n_words, hipStream_t s) {
     if (n_words <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((n_words + 255) / 256, 8192);
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n_words, 0u);
-    return hipGetLastError();
+    GS_CHECK_LAUNCH("k_fill_u32");
+    return hipSuccess;
 }
 
 template <typename F>
@@ -406,9 +431,12 @@ hipError_t by_precision(int p, F f) {
 }
 
 template <int P, int TS>
-hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, const Workspace& ws,
-                       int64_t ld, hipStream_t s) {
-    const dim3 grid((unsigned)((ix.n_docs + (1 << TS) - 1) >> TS), (unsigned)qt);
+hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, int order,
+                       const Workspace& ws, int64_t ld, hipStream_t s) {
+    const int64_t n_tiles = (ix.n_docs + (1 << TS) - 1) >> TS;
+    const int64_t blocks1d = ((n_tiles + 7) / 8) * 8 * (int64_t)qt;
+    if (order != 0 && blocks1d * 512 >= ((int64_t)1 << 32)) return hipErrorInvalidConfiguration;
+    const dim3 grid = order == 0 ? dim3((unsigned)n_tiles, (unsigned)qt) : dim3((unsigned)blocks1d);
     const size_t lds = (size_t)((1 << TS) * (P == kU8 ? 1 : 2) + kHistBins) * 4;
     if (lds > 150 * 1024) return hipErrorInvalidValue;
     if (lds > 65536) {
@@ -421,17 +449,21 @@ hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32
                 if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             return e;
         }();
-        if (attr != hipSuccess) return attr;
+        if (attr != hipSuccess) {
+            g_failed_launch = "hipFuncSetAttribute(k_score_tiled)";
+            return attr;
+        }
     }
     switch (chunk) {
-        case 64: hipLaunchKernelGGL((k_score_tiled<P, TS, 64>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
-        case 128: hipLaunchKernelGGL((k_score_tiled<P, TS, 128>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
-        case 256: hipLaunchKernelGGL((k_score_tiled<P, TS, 256>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
-        case 512: hipLaunchKernelGGL((k_score_tiled<P, TS, 512>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
-        case 1024: hipLaunchKernelGGL((k_score_tiled<P, TS, 1024>), grid, dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1); break;
+        case 64: hipLaunchKernelGGL((k_score_tiled<P, TS, 64>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
+        case 128: hipLaunchKernelGGL((k_score_tiled<P, TS, 128>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
+        case 256: hipLaunchKernelGGL((k_score_tiled<P, TS, 256>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
+        case 512: hipLaunchKernelGGL((k_score_tiled<P, TS, 512>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
+        case 1024: hipLaunchKernelGGL((k_score_tiled<P, TS, 1024>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    GS_CHECK_LAUNCH("k_score_tiled");
+    return hipSuccess;
 }
 
 }  // namespace
@@ -441,7 +473,8 @@ int64_t score_ld(int64_t n_docs) { return (n_docs + 63) / 64 * 64; }
 hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s) {
     if (n16 <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy16, dim3(4096), dim3(256), 0, s, (uint4*)dst, (const uint4*)src, n16);
-    return hipGetLastError();
+    GS_CHECK_LAUNCH("k_copy16");
+    return hipSuccess;
 }
 
 hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s) {
@@ -456,11 +489,12 @@ hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0
     const int64_t ld = score_ld(ix.n_docs);
     return by_precision(ix.precision, [&](auto pc) -> hipError_t {
         constexpr int P = decltype(pc)::value;
+        const int order = o.kernel == 4 ? 1 : 0;  // GS_KERNEL_SHARED: tile-major, XCD-aware
         switch (o.tile_shift) {
-            case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, ws, ld, s);
-            case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, ws, ld, s);
+            case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, order, ws, ld, s);
+            case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, order, ws, ld, s);
             case 15:
-                if constexpr (P == kU8) return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, ws, ld, s);
+                if constexpr (P == kU8) return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, order, ws, ld, s);
                 return hipErrorInvalidValue;  // 32768 fixed-point accumulators exceed one CU's LDS
         }
         return hipErrorInvalidValue;
@@ -475,7 +509,7 @@ hipError_t launch_score_atomic(const DevIndex& ix, const DevBatch& qb, int32_t q
     int64_t* prefix = ws.work_prefix;
     int32_t* pair_q = ws.work_pair_q;
     hipLaunchKernelGGL(k_pair_prefix, dim3(1), dim3(1024), 0, s, ix, qb, q0, qt, o.chunk, prefix, pair_q);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    GS_CHECK_LAUNCH("k_pair_prefix");
     const dim3 grid(2048);
     e = by_precision(ix.precision, [&](auto pc) -> hipError_t {
         constexpr int P = decltype(pc)::value;
@@ -487,7 +521,8 @@ hipError_t launch_score_atomic(const DevIndex& ix, const DevBatch& qb, int32_t q
             case 1024: hipLaunchKernelGGL((k_score_atomic<P, 1024>), grid, dim3(256), 0, s, ix, qb, q0, qt, prefix, pair_q, ws.scores, ld); break;
             default: return hipErrorInvalidValue;
         }
-        return hipGetLastError();
+        GS_CHECK_LAUNCH("k_score_atomic");
+        return hipSuccess;
     });
     if (e != hipSuccess) return e;
     return launch_hist1(ix, qb, q0, qt, ws, s);
@@ -509,7 +544,8 @@ hipError_t launch_score_docpar(const DevIndex& ix, const DevBatch& qb, int32_t q
             if (a != hipSuccess) return a;
         }
         hipLaunchKernelGGL((k_score_docpar<P>), grid, dim3(1024), lds, s, ix, qb, q0, ws.scores, ld, per);
-        return hipGetLastError();
+        GS_CHECK_LAUNCH("k_score_docpar");
+        return hipSuccess;
     });
     if (e != hipSuccess) return e;
     return launch_hist1(ix, qb, q0, qt, ws, s);
@@ -522,7 +558,8 @@ hipError_t launch_hist1(const DevIndex& ix, const DevBatch& qb, int32_t q0, int3
     const dim3 grid((unsigned)((ix.n_docs + per - 1) / per), (unsigned)qt);
     hipLaunchKernelGGL(k_hist1, grid, dim3(512), 0, s, qb, q0, ix.n_docs, (const uint32_t*)ws.scores, ld, per,
                        ws.hist1);
-    return hipGetLastError();
+    GS_CHECK_LAUNCH("k_hist1");
+    return hipSuccess;
 }
 
 }  // namespace gs

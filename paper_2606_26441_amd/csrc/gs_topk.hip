@@ -464,8 +464,8 @@ hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int
     const dim3 grid_scan((unsigned)((N + per - 1) / per), (unsigned)qt);
     hipLaunchKernelGGL(k_select_first, dim3(qt), dim3(64), 0, s, qb, q0, N, ix.precision,
                        (const uint32_t*)ws.hist1, ws.state);
-    hipError_t e = hipGetLastError();
-    auto final_pass = [&]() {
+    GS_CHECK_LAUNCH("k_select_first");
+    auto final_pass = [&]() -> hipError_t {
         switch (ix.precision) {
             case kFP32:
                 hipLaunchKernelGGL(k_final<kFP32>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
@@ -480,31 +480,35 @@ hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int
                                    (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores);
                 break;
         }
-        return hipGetLastError();
+        GS_CHECK_LAUNCH("k_final");
+        return hipSuccess;
     };
-    if (N == 0) return e == hipSuccess ? final_pass() : e;  // empty collection: padding only
-    for (int p = 0; p < kRefinePasses && e == hipSuccess; p++) {
+    if (N == 0) return final_pass();  // empty collection: padding only
+    for (int p = 0; p < kRefinePasses; p++) {
         hipLaunchKernelGGL(k_refine_hist, grid_scan, dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores, ws.ld, per,
                            (const SelState*)ws.state, ws.hist_ref);
+        GS_CHECK_LAUNCH("k_refine_hist");
         hipLaunchKernelGGL(k_refine_select, dim3(qt), dim3(64), 0, s, qb, q0, N, ws.hist_ref, ws.state);
-        e = hipGetLastError();
+        GS_CHECK_LAUNCH("k_refine_select");
     }
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_filter, grid_scan, dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores, ws.ld, per, ws.state,
                        ws.cand);
-    if ((e = final_pass()) != hipSuccess) return e;
+    GS_CHECK_LAUNCH("k_filter");
+    hipError_t e = final_pass();
+    if (e != hipSuccess) return e;
     if (ix.precision == kBF16) {
         hipLaunchKernelGGL(k_band_filter, grid_scan, dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores, ws.ld, per,
                            ws.state, ws.band_id);
+        GS_CHECK_LAUNCH("k_band_filter");
         hipLaunchKernelGGL(k_band_final, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state, ws.band_s, ws.band_id,
                            out_ids, (double*)out_scores);
+        GS_CHECK_LAUNCH("k_band_final");
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (diag) {
         hipLaunchKernelGGL(k_diag, dim3((qt + 255) / 256), dim3(256), 0, s, q0, qt, (const SelState*)ws.state, diag);
-        e = hipGetLastError();
+        GS_CHECK_LAUNCH("k_diag");
     }
-    return e;
+    return hipSuccess;
 }
 
 }  // namespace gs

@@ -19,7 +19,7 @@ from parity_rules import check_batch, check_exact_f64, check_exact_int
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-KERNELS = ["tiled", "atomic", "docpar"]
+KERNELS = ["tiled", "atomic", "docpar", "shared"]
 
 
 def _gs():
@@ -84,7 +84,7 @@ def test_dyadic_weights_are_exact_across_tiles(precision, tile_docs, chunk):
         rid, rsc = oracle.topk_i64(docs, qs, 300)
     else:
         rid, rsc = oracle.topk_f64(docs, qs, 300)
-    kernels = ("tiled", "atomic") if precision == "fp32" else ("tiled",)
+    kernels = ("tiled", "atomic", "shared") if precision == "fp32" else ("tiled", "shared")
     for kernel in kernels:
         ids, sc, _ = _run(gs, docs, qs, 300, precision, kernel, tile_docs=tile_docs, chunk=chunk)
         for q in range(qs.n_rows):
@@ -151,12 +151,15 @@ def test_k_beyond_collection_and_tiny_collections(precision):
             check_batch(precision, docs, qs, ids, sc, [n + 3, max(1, n // 2), n], what="n%d %s" % (n, kernel))
 
 
-def test_query_tiling_matches_one_tile(tiny):
+@pytest.mark.parametrize("precision", ["u8", "fp32"])
+def test_query_tiling_and_block_order_do_not_change_results(tiny, precision):
+    # integer sums (uint8 impacts, and the fixed-point fp32 accumulators) do not depend on update order
     gs = _gs()
     docs, qs = tiny
-    a, sa, _ = _run(gs, docs, qs, 100, "u8", "tiled", query_tile=3)
-    b, sb, _ = _run(gs, docs, qs, 100, "u8", "tiled", query_tile=0)
-    same = np.array_equal(a, b) and np.array_equal(sa, sb)
+    a, sa, _ = _run(gs, docs, qs, 100, precision, "tiled", query_tile=3)
+    b, sb, _ = _run(gs, docs, qs, 100, precision, "tiled", query_tile=0)
+    c, sc, _ = _run(gs, docs, qs, 100, precision, "shared", query_tile=5)
+    same = all(np.array_equal(x, y) for x, y in ((a, b), (sa, sb), (a, c), (sa, sc)))
     assert same
 
 
@@ -199,7 +202,8 @@ def mid():
 
 
 @pytest.mark.parametrize("precision,kernel", [("fp32", "tiled"), ("fp32", "atomic"), ("fp32", "docpar"),
-                                              ("u8", "tiled"), ("bf16", "tiled")])
+                                              ("fp32", "shared"), ("u8", "tiled"), ("u8", "shared"),
+                                              ("bf16", "tiled"), ("bf16", "shared")])
 def test_mid_scale_top1000(mid, precision, kernel):
     gs = _gs()
     docs, qs = mid
