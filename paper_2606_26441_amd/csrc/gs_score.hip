@@ -9,8 +9,8 @@
 //    workgroup streams every segment of its query through coalesced loads and
 //    scatter-adds w_q * w_d into an LDS copy of the tile with LDS atomics, then
 //    writes the tile once (coalesced) and builds the histogram of the first
-//    selection digit. No global atomics, no zeroing pass. This is the
-//    "shared-memory accumulation" hybrid the paper names as future work (1).
+//    selection digit. No global atomics, no zeroing pass. This is the hybrid
+//    of scatter-add and on-chip accumulation listed as future work (1) in Sec. 8.
 //  * k_score_atomic - term-parallel, work = (query, term, chunk of postings);
 //    global atomic adds into a zeroed score array, as in the paper's Sec. 5.2
 //    kernel (one program per query term looping over posting chunks), with
