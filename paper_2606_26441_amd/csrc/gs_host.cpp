@@ -291,6 +291,7 @@ struct gs_index_s {
     uint32_t flags = 0;
     size_t bytes = 0;
     std::vector<float> term_max;  // largest stored weight of each term (value of the stored form)
+    std::vector<int32_t> term_len;  // postings per term (host copy, for work estimates)
     std::vector<void*> allocs;
     DevIndex dev{};
     ~gs_index_s() {
@@ -395,6 +396,8 @@ size_t workspace_bytes(int64_t n_docs, int32_t qt, int32_t precision) {
     }
     b += align256(((size_t)qt * kMaxQueryNnz + 1) * 8);
     b += align256((size_t)qt * kMaxQueryNnz * 4);
+    b += align256((size_t)qt * 4);
+    b += align256(8 * 4);
     return b;
 }
 
@@ -420,6 +423,8 @@ void carve_workspace(void* base, int64_t n_docs, int32_t qt, int32_t precision, 
     }
     ws->work_prefix = (int64_t*)take(((size_t)qt * kMaxQueryNnz + 1) * 8);
     ws->work_pair_q = (int32_t*)take((size_t)qt * kMaxQueryNnz * 4);
+    ws->order = (int32_t*)take((size_t)qt * 4);
+    ws->counters = (uint32_t*)take(8 * 4);
 }
 
 }  // namespace gs
@@ -502,6 +507,7 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     ix->precision = precision;
     if (precision == kBF16) flags |= GS_KEEP_FORWARD;
     ix->flags = flags;
+    ix->term_len = L.term_len;
     ix->term_max.assign((size_t)vocab_size, 0.0f);
     for (int32_t v = 0; v < vocab_size; v++)
         for (int64_t k = L.term_off[(size_t)v] / kBlock; k < L.term_off[(size_t)v + 1] / kBlock; k++)
@@ -610,18 +616,20 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
     };
     std::vector<int64_t> rp(q_row_ptr ? q_row_ptr : nullptr, q_row_ptr ? q_row_ptr + n_queries + 1 : nullptr);
     if (rp.empty()) rp.push_back(0);
-    std::vector<int32_t> w8((size_t)q_nnz), fshift((size_t)n_queries), qsh((size_t)q_nnz);
-    std::vector<uint32_t> qm((size_t)q_nnz);
+    std::vector<int32_t> w8((size_t)q_nnz), fshift((size_t)n_queries);
+    std::vector<double> qfx((size_t)q_nnz);
     std::vector<float> delta((size_t)n_queries);
     std::vector<double> qscale((size_t)n_queries), qerr((size_t)n_queries);
+    std::vector<int64_t> qwork((size_t)n_queries, 0);
     for (int32_t q = 0; q < n_queries; q++) {
         uint64_t maxs = 0;
-        double maxscore = 0.0;
+        double maxprod = 0.0;
         const int64_t m = rp[(size_t)q + 1] - rp[(size_t)q];
         for (int64_t j = rp[(size_t)q]; j < rp[(size_t)q + 1]; j++) {
+            qwork[(size_t)q] += ix->term_len[(size_t)r.term[j]];
             w8[(size_t)j] = q8(r.w[j]);
             maxs += (uint64_t)w8[(size_t)j] * 255u;
-            maxscore += (double)r.w[j] * (double)ix->term_max[(size_t)r.term[j]];
+            maxprod = std::max(maxprod, (double)r.w[j] * (double)ix->term_max[(size_t)r.term[j]]);
         }
         if (ix->precision == kU8) {
             int hb = 0;
@@ -630,19 +638,15 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
         } else {
             fshift[(size_t)q] = kFirstShiftFloat;
         }
-        // fixed point: units of 2^-F with every sum of this query's products below 2^62
+        // fixed point: units of 2^-F with every product of this query below 2^51 units
+        // (so a sum of at most 256 products stays below 2^59)
         int ex = 0;
-        if (maxscore > 0.0) (void)std::frexp(maxscore * (1.0 + 1e-9), &ex);  // maxscore < 2^ex
-        const int F = std::min(960, std::max(-60, 62 - ex));
+        if (maxprod > 0.0) (void)std::frexp(maxprod * (1.0 + 1e-9), &ex);  // maxprod < 2^ex
+        const int F = std::min(1000, std::max(-1000, 51 - ex));
         qscale[(size_t)q] = std::ldexp(1.0, -F);
-        qerr[(size_t)q] = (double)(m + 1) * std::ldexp(1.0, -F) * (1.0 + 1e-6);  // products round up
-        for (int64_t j = rp[(size_t)q]; j < rp[(size_t)q + 1]; j++) {
-            uint32_t bits;
-            std::memcpy(&bits, &r.w[j], 4);
-            const uint32_t ef = (bits >> 23) & 0xffu;
-            qm[(size_t)j] = (bits & 0x7fffffu) | (ef ? 0x800000u : 0u);
-            qsh[(size_t)j] = (int32_t)(ef ? ef : 1u) - 300 + F;
-        }
+        // each product is within half a unit (or, raised from 0 to 1, within one unit) of exact
+        qerr[(size_t)q] = (double)(m + 1) * std::ldexp(1.0, -F) * (1.0 + 1e-6);
+        for (int64_t j = rp[(size_t)q]; j < rp[(size_t)q + 1]; j++) qfx[(size_t)j] = std::ldexp((double)r.w[j], F);
         // bf16 form: relative error of a stored weight (2^-8) and of the fp32 score (2^-24, with margin)
         delta[(size_t)q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -23)) - 1.0) * (1.0 + 1e-6));
     }
@@ -657,13 +661,12 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
     if ((rc = dev_upload(b->allocs, bytes, k, (size_t)n_queries, &d_k, s))) return done(rc);
     if ((rc = dev_upload(b->allocs, bytes, fshift.data(), fshift.size(), &d_fs, s))) return done(rc);
     if ((rc = dev_upload(b->allocs, bytes, delta.data(), delta.size(), &d_delta, s))) return done(rc);
-    uint32_t* d_qm = nullptr;
-    int32_t* d_qsh = nullptr;
-    double *d_qscale = nullptr, *d_qerr = nullptr;
-    if ((rc = dev_upload(b->allocs, bytes, qm.data(), qm.size(), &d_qm, s))) return done(rc);
-    if ((rc = dev_upload(b->allocs, bytes, qsh.data(), qsh.size(), &d_qsh, s))) return done(rc);
+    double *d_qfx = nullptr, *d_qscale = nullptr, *d_qerr = nullptr;
+    if ((rc = dev_upload(b->allocs, bytes, qfx.data(), qfx.size(), &d_qfx, s))) return done(rc);
     if ((rc = dev_upload(b->allocs, bytes, qscale.data(), qscale.size(), &d_qscale, s))) return done(rc);
     if ((rc = dev_upload(b->allocs, bytes, qerr.data(), qerr.size(), &d_qerr, s))) return done(rc);
+    int64_t* d_qwork = nullptr;
+    if ((rc = dev_upload(b->allocs, bytes, qwork.data(), qwork.size(), &d_qwork, s))) return done(rc);
     if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, (size_t)n_queries * 4, &b->diag, s))) return done(rc);
     hipError_t e = hipMemsetAsync(b->diag, 0, (size_t)std::max(n_queries, 1) * 16, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -678,10 +681,10 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
     d.k = d_k;
     d.first_shift = d_fs;
     d.delta = d_delta;
-    d.q_m = d_qm;
-    d.q_sh = d_qsh;
+    d.q_fx = d_qfx;
     d.q_scale = d_qscale;
     d.q_abs_err = d_qerr;
+    d.q_work = d_qwork;
     *out = b;
     return GS_OK;
 }

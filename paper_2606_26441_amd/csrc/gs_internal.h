@@ -59,13 +59,13 @@ struct DevBatch {
     const int32_t* k;          // [n]
     const int32_t* first_shift;  // [n] position of the first selection digit in the composite key
     const float* delta;        // [n] bf16 relative error bound per query (GS_BF16), else null
-    // fixed-point accumulation (GS_FP32, GS_BF16): a product w_q * w_d is formed exactly from the
-    // integer significands, m_q * m_d * 2^(q_sh + e_d), and summed as an unsigned 64-bit integer in
-    // units of 2^-F(q); F(q) is chosen per query so that no sum can reach 2^62.
-    const uint32_t* q_m;       // [q_nnz] significand of w_q (24 bits, hidden bit included)
-    const int32_t* q_sh;       // [q_nnz] exponent of w_q - 300 + F(q)
+    // fixed-point accumulation (GS_FP32, GS_BF16): each product w_q * w_d is rounded to an
+    // integer number of units 2^-F(q) and summed exactly as an unsigned 64-bit integer; F(q) is
+    // chosen per query so that every product of the query stays below 2^51 units.
+    const double* q_fx;        // [q_nnz] w_q * 2^F(q) (exact)
     const double* q_scale;     // [n] 2^-F(q)
-    const double* q_abs_err;   // [n] bound on fixed-point sum - exact sum (>= 0: products round up)
+    const double* q_abs_err;   // [n] bound on |fixed-point sum - exact sum|
+    const int64_t* q_work;     // [n] postings of the query's terms (work estimate)
 };
 
 // Per-query selection state in the workspace.
@@ -94,6 +94,8 @@ struct Workspace {
     int32_t* band_id;             // [qt][kCandCap] (bf16)
     int64_t* work_prefix;         // [qt * kMaxQueryNnz + 1] (atomic kernel)
     int32_t* work_pair_q;         // [qt * kMaxQueryNnz]
+    int32_t* order;               // [qt] persistent kernel: query order within the tile
+    uint32_t* counters;           // [8] persistent kernel: per-XCD work counters
     int64_t ld;                   // row stride of the score arrays (n_docs rounded up to 64)
 };
 

@@ -78,21 +78,19 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// Fixed-point product of a query weight (significand qm, shift qsh = e_q - 300 + F)
-// and a stored document weight given by its fp32 bit pattern (bf16 weights are
-// widened first): m_q * m_d * 2^(qsh + e_d) rounded UP to an integer, so a
-// product is zero exactly when w_q * w_d is zero and the sum never undershoots.
-// The per-query F guarantees that any sum of a query's products stays below 2^62.
-__device__ __forceinline__ unsigned long long fx_product(uint32_t qm, int qsh, uint32_t wbits) {
-    const uint32_t ef = (wbits >> 23) & 0xffu;
-    const uint32_t md = (wbits & 0x7fffffu) | (ef ? 0x800000u : 0u);
-    const int sh = qsh + (int)(ef ? ef : 1u);
-    const unsigned long long M = (unsigned long long)qm * md;
-    const int sl = sh > 0 ? sh : 0;
-    const int sr = sh < 0 ? (-sh < 62 ? -sh : 62) : 0;
-    const unsigned long long left = M << sl;
-    const unsigned long long right = (M + ((1ull << sr) - 1ull)) >> sr;
-    return sh >= 0 ? left : (-sh > 62 ? (M != 0ull ? 1ull : 0ull) : right);
+// Fixed-point product of a query weight pre-scaled by 2^F (qd = w_q * 2^F, exact
+// in fp64) and a stored document weight given by its fp32 bit pattern (bf16
+// weights are widened first). One fp64 FMA forms qd * w_d + 2^52 with a single
+// rounding; the per-query F keeps every product below 2^51, so the result lies in
+// [2^52, 2^53) where the fp64 spacing is 1 and its low bits are the product
+// rounded to the nearest integer. A positive product that rounds to 0 is raised
+// to 1, so a product is zero exactly when w_q * w_d is zero.
+__device__ __forceinline__ unsigned long long fx_product(double qd, uint32_t wbits) {
+    constexpr double kTwo52 = 4503599627370496.0;
+    const double wd = (double)__uint_as_float(wbits);
+    const unsigned long long r =
+        (unsigned long long)__double_as_longlong(__builtin_fma(qd, wd, kTwo52)) - 0x4330000000000000ull;
+    return r | (unsigned long long)((r == 0ull) & (wbits != 0u));  // qd > 0 for every processed term
 }
 
 __device__ __forceinline__ uint32_t stored_bits(const void* p, int64_t i, std::integral_constant<int, kFP32>) {
@@ -146,44 +144,43 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
 // of CH postings; wavefronts take chunks round-robin, each lane loads CH/64
 // postings (coalesced across the wavefront) before issuing its LDS adds.
 
-// Block order. Query-major (order 0): grid (tiles, queries), the tiles of one
-// query are consecutive, so every query streams its own postings from HBM.
-// Tile-major, XCD-aware (order 1): a 1-D grid in which workgroup b runs on XCD
-// b % 8 (round-robin dispatch); XCD x takes the tiles x, x+8, x+16, ... and runs
-// every query of the tile before the next tile, so a tile's posting segments are
-// fetched from HBM once and re-read by the other queries from that XCD's L2 and
-// the shared last-level cache (shared traversal of common terms).
-__device__ __forceinline__ bool block_coords(int order, int32_t qt, int64_t n_tiles, int64_t* tile, int* ql) {
-    if (order == 0) {
-        *tile = blockIdx.x;
-        *ql = (int)blockIdx.y;
-        return true;
+struct TileShared {
+    int64_t seg_beg[kMaxQueryNnz];
+    int32_t seg_len[kMaxQueryNnz];
+    int32_t seg_cpre[kMaxQueryNnz + 1];
+    double seg_qd[kMaxQueryNnz];   // w_q * 2^F (fixed point)
+    uint32_t seg_q8[kMaxQueryNnz]; // uint8 query impact
+};
+
+// Chunk c of a tile's work (c is the same on every lane of the wavefront):
+// segment index, first posting and length, kept in scalar registers.
+__device__ __forceinline__ void chunk_at(const TileShared& sh, int nq, int c, int ch, int* seg, int64_t* p0, int* n) {
+    int lo = 0, hi = nq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sh.seg_cpre[mid] <= c) lo = mid; else hi = mid - 1;
     }
-    const int64_t b = blockIdx.x;
-    const int64_t x = b & 7, r = b >> 3;
-    *tile = (r / qt) * 8 + x;
-    *ql = (int)(r % qt);
-    return *tile < n_tiles;
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const int off = (c - sh.seg_cpre[lo]) * ch;
+    *seg = lo;
+    *n = __builtin_amdgcn_readfirstlane(min(ch, sh.seg_len[lo] - off));
+    const int64_t p = sh.seg_beg[lo] + off;
+    *p0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(p >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)p));
 }
 
+// Score one (query, doc tile) work item into LDS and flush it. Every thread of
+// the workgroup calls this; it ends after the flush (callers that loop must
+// synchronise before reusing the LDS).
 template <int P, int TS, int CH>
-__global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, int32_t q0, int32_t qt, int order,
-                                                     uint32_t* __restrict__ S, int64_t ld,
-                                                     uint32_t* __restrict__ hist1) {
+__device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& qb, int32_t q0, int64_t tile, int ql,
+                                           uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
+                                           uint32_t* lds, TileShared& sh) {
     constexpr int BS = 512, NW = BS / kWave, TILE = 1 << TS, U = CH / kWave, GPT = TS - kGrainShift;
     constexpr bool FX = P != kU8;
-    int64_t tile;
-    int ql;
-    if (!block_coords(order, qt, (ix.n_docs + TILE - 1) >> TS, &tile, &ql)) return;
-    extern __shared__ __align__(16) uint32_t lds[];
     unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(lds);  // [TILE] (FX)
     uint32_t* acc32 = lds;                                                   // [TILE] (uint8)
     uint32_t* hist = lds + TILE * (FX ? 2 : 1);                               // [kHistBins]
-    __shared__ int64_t seg_beg[kMaxQueryNnz];
-    __shared__ int32_t seg_len[kMaxQueryNnz];
-    __shared__ int32_t seg_cpre[kMaxQueryNnz + 1];
-    __shared__ uint32_t seg_a[kMaxQueryNnz];  // q_m (fixed point) or the uint8 query impact
-    __shared__ int32_t seg_b[kMaxQueryNnz];   // q_sh (fixed point)
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const int q = q0 + ql;
@@ -202,14 +199,16 @@ __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, i
         const int term = qb.q_term[qa + t];
         const int32_t* row = ix.tile_off + (int64_t)term * (ix.n_grains + 1);
         const int a = row[g0], b = row[g1];
-        seg_beg[t] = ix.term_off[term] + a;
-        seg_len[t] = b - a;
+        sh.seg_beg[t] = ix.term_off[term] + a;
+        bool zero_weight;
         if constexpr (FX) {
-            seg_a[t] = qb.q_m[qa + t];
-            seg_b[t] = qb.q_sh[qa + t];
+            sh.seg_qd[t] = qb.q_fx[qa + t];
+            zero_weight = !(sh.seg_qd[t] > 0.0);
         } else {
-            seg_a[t] = (uint32_t)qb.q_w8[qa + t];
+            sh.seg_q8[t] = (uint32_t)qb.q_w8[qa + t];
+            zero_weight = sh.seg_q8[t] == 0u;
         }
+        sh.seg_len[t] = zero_weight ? 0 : b - a;  // a zero query weight adds nothing
     }
     __syncthreads();
     if (wave == 0) {
@@ -218,7 +217,7 @@ __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, i
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int t = lane * 4 + u;
-            c[u] = t < nq ? (seg_len[t] + CH - 1) / CH : 0;
+            c[u] = t < nq ? (sh.seg_len[t] + CH - 1) / CH : 0;
             s += c[u];
         }
         int incl = s;
@@ -230,50 +229,123 @@ __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, i
         int run = incl - s;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            seg_cpre[lane * 4 + u] = run;
+            sh.seg_cpre[lane * 4 + u] = run;
             run += c[u];
         }
         const int total = __shfl(incl, kWave - 1, kWave);
-        if (lane == 0) seg_cpre[kMaxQueryNnz] = total;
+        if (lane == 0) sh.seg_cpre[kMaxQueryNnz] = total;
     }
     __syncthreads();
 
-    const int total = seg_cpre[nq];
-    for (int c = wave; c < total; c += NW) {
-        int lo = 0, hi = nq - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (seg_cpre[mid] <= c) lo = mid; else hi = mid - 1;
-        }
-        const int off = (c - seg_cpre[lo]) * CH;
-        const int n = min(CH, seg_len[lo] - off);
-        const int64_t p0 = seg_beg[lo] + off;
-        const uint32_t qa_ = seg_a[lo];
-        const int qb_ = seg_b[lo];
+    // Chunks go round-robin to the wavefronts. Each wavefront keeps two chunks in
+    // flight: the loads of its next chunk are issued before the LDS adds of the
+    // current one (two register sets, alternating).
+    const int total = sh.seg_cpre[nq];
+    struct Chunk {
         int doc[U];
-        uint32_t wb[U];
+        uint32_t w[U];
+        int seg, n;
+    };
+    // Loads are straight-line (no branch around them, so the compiler can wait for
+    // the older chunk only): lanes past the end of a chunk re-read its last posting,
+    // and an empty slot reads posting 0 (the arrays are never empty).
+    auto load = [&](int c, Chunk& k, bool valid) {
+        int64_t p0 = 0;
+        k.seg = 0;
+        k.n = 0;
+        if (valid) chunk_at(sh, nq, c, CH, &k.seg, &p0, &k.n);
+        const int last = max(k.n - 1, 0);
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int i = lane + u * kWave;
-            doc[u] = (int)base;
-            wb[u] = 0u;
-            if (i < n) {
-                doc[u] = ix.post_doc[p0 + i];
-                if constexpr (P == kU8) wb[u] = ((const uint8_t*)ix.post_w)[p0 + i];
-                else wb[u] = stored_bits(ix.post_w, p0 + i, std::integral_constant<int, P>());
-            }
+            const int64_t p = p0 + min(lane + u * kWave, last);
+            k.doc[u] = ix.post_doc[p];
+            if constexpr (P == kU8) k.w[u] = ((const uint8_t*)ix.post_w)[p];
+            else k.w[u] = stored_bits(ix.post_w, p, std::integral_constant<int, P>());
         }
+    };
+    auto apply = [&](const Chunk& k) {
+        if constexpr (FX) {
+            const double qd = sh.seg_qd[k.seg];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            if (lane + u * kWave < n) {
-                if constexpr (FX) atomicAdd(&acc64[doc[u] - base], fx_product(qa_, qb_, wb[u]));
-                else atomicAdd(&acc32[doc[u] - base], qa_ * wb[u]);
-            }
+            for (int u = 0; u < U; u++)
+                if (lane + u * kWave < k.n) atomicAdd(&acc64[k.doc[u] - base], fx_product(qd, k.w[u]));
+        } else {
+            const uint32_t q8v = sh.seg_q8[k.seg];
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - base], q8v * k.w[u]);
         }
+    };
+    Chunk A, B;
+    int c = wave;
+    load(c, A, c < total);
+    while (c < total) {
+        const int cb = c + NW;
+        load(cb, B, cb < total);
+        apply(A);
+        if (cb >= total) break;
+        const int ca = cb + NW;
+        load(ca, A, ca < total);
+        apply(B);
+        c = ca;
     }
     __syncthreads();
     flush_tile<BS, FX>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
                        FX ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins);
+}
+
+// Per-query form: grid (tiles, queries), the tiles of one query are consecutive
+// workgroups, so each query streams its own postings from HBM.
+template <int P, int TS, int CH>
+__global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
+                                                     int64_t ld, uint32_t* __restrict__ hist1) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ TileShared sh;
+    score_tile<P, TS, CH>(ix, qb, q0, (int64_t)blockIdx.x, (int)blockIdx.y, S, ld, hist1, lds, sh);
+}
+
+// Persistent form of the shared traversal: a grid of (resident workgroups,
+// rounded to a multiple of 8) in which workgroup b stays on XCD b % 8 and pulls
+// work items from that XCD's counter. XCD x owns the tiles x, x+8, ...; the items
+// of a tile are its queries in the order given by `order` (heaviest first), so
+// every query of a tile runs on one XCD while the tile's postings are in its L2.
+// Every workgroup leaves the loop once its XCD's counter passes the item count.
+template <int P, int TS, int CH>
+__global__ __launch_bounds__(512) void k_score_persistent(DevIndex ix, DevBatch qb, int32_t q0, int32_t qt,
+                                                          const int32_t* __restrict__ order,
+                                                          uint32_t* __restrict__ counters, uint32_t* __restrict__ S,
+                                                          int64_t ld, uint32_t* __restrict__ hist1) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ TileShared sh;
+    __shared__ int64_t item_sh;
+    const int x = (int)(blockIdx.x & 7);
+    const int64_t n_tiles = (ix.n_docs + (1 << TS) - 1) >> TS;
+    const int64_t tiles_x = n_tiles > x ? (n_tiles - x + 7) / 8 : 0;
+    const int64_t items = tiles_x * qt;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(&counters[x], 1u);
+        __syncthreads();
+        const int64_t item = item_sh;
+        if (item >= items) break;
+        const int64_t tile = x + 8 * (item / qt);
+        const int ql = order[item % qt];
+        score_tile<P, TS, CH>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh);
+        __syncthreads();
+    }
+}
+
+// Work order of a query tile for the persistent kernel: local query indices by
+// descending estimated work (postings of the query's terms), ties by index.
+__global__ __launch_bounds__(256) void k_work_order(DevBatch qb, int32_t q0, int32_t qt, int32_t* __restrict__ order) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= qt) return;
+    const int64_t wi = qb.q_work[q0 + i];
+    int r = 0;
+    for (int j = 0; j < qt; j++) {
+        const int64_t wj = qb.q_work[q0 + j];
+        r += (wj > wi) || (wj == wi && j < i);
+    }
+    order[r] = i;
 }
 
 // ------------------------------------------------------------ atomic --
@@ -430,23 +502,19 @@ hipError_t by_precision(int p, F f) {
     return hipErrorInvalidValue;
 }
 
-template <int P, int TS>
-hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, int order,
-                       const Workspace& ws, int64_t ld, hipStream_t s) {
+template <int P, int TS, int CH>
+hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, bool persistent,
+                            const Workspace& ws, int64_t ld, hipStream_t s) {
     const int64_t n_tiles = (ix.n_docs + (1 << TS) - 1) >> TS;
-    const int64_t blocks1d = ((n_tiles + 7) / 8) * 8 * (int64_t)qt;
-    if (order != 0 && blocks1d * 512 >= ((int64_t)1 << 32)) return hipErrorInvalidConfiguration;
-    const dim3 grid = order == 0 ? dim3((unsigned)n_tiles, (unsigned)qt) : dim3((unsigned)blocks1d);
     const size_t lds = (size_t)((1 << TS) * (P == kU8 ? 1 : 2) + kHistBins) * 4;
     if (lds > 150 * 1024) return hipErrorInvalidValue;
     if (lds > 65536) {
         static const hipError_t attr = [&] {
-            hipError_t e = hipSuccess;
-            const void* fns[] = {(const void*)k_score_tiled<P, TS, 64>, (const void*)k_score_tiled<P, TS, 128>,
-                                 (const void*)k_score_tiled<P, TS, 256>, (const void*)k_score_tiled<P, TS, 512>,
-                                 (const void*)k_score_tiled<P, TS, 1024>};
-            for (const void* f : fns)
-                if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipError_t e = hipFuncSetAttribute((const void*)k_score_tiled<P, TS, CH>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute((const void*)k_score_persistent<P, TS, CH>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             return e;
         }();
         if (attr != hipSuccess) {
@@ -454,16 +522,42 @@ hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32
             return attr;
         }
     }
-    switch (chunk) {
-        case 64: hipLaunchKernelGGL((k_score_tiled<P, TS, 64>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
-        case 128: hipLaunchKernelGGL((k_score_tiled<P, TS, 128>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
-        case 256: hipLaunchKernelGGL((k_score_tiled<P, TS, 256>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
-        case 512: hipLaunchKernelGGL((k_score_tiled<P, TS, 512>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
-        case 1024: hipLaunchKernelGGL((k_score_tiled<P, TS, 1024>), grid, dim3(512), lds, s, ix, qb, q0, qt, order, ws.scores, ld, ws.hist1); break;
-        default: return hipErrorInvalidValue;
+    if (!persistent) {
+        hipLaunchKernelGGL((k_score_tiled<P, TS, CH>), dim3((unsigned)n_tiles, (unsigned)qt), dim3(512), lds, s, ix,
+                           qb, q0, ws.scores, ld, ws.hist1);
+        GS_CHECK_LAUNCH("k_score_tiled");
+        return hipSuccess;
     }
-    GS_CHECK_LAUNCH("k_score_tiled");
+    // resident workgroups: as many as fit on every CU at once, a multiple of the 8 XCDs
+    static const int grid = [&] {
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t p{};
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_score_persistent<P, TS, CH>, 512,
+                                                         lds) != hipSuccess)
+            return 0;
+        return std::max(8, (p.multiProcessorCount * std::max(per_cu, 1)) / 8 * 8);
+    }();
+    if (grid <= 0) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_work_order, dim3((unsigned)((qt + 255) / 256)), dim3(256), 0, s, qb, q0, qt, ws.order);
+    GS_CHECK_LAUNCH("k_work_order");
+    hipLaunchKernelGGL((k_score_persistent<P, TS, CH>), dim3((unsigned)grid), dim3(512), lds, s, ix, qb, q0, qt,
+                       (const int32_t*)ws.order, ws.counters, ws.scores, ld, ws.hist1);
+    GS_CHECK_LAUNCH("k_score_persistent");
     return hipSuccess;
+}
+
+template <int P, int TS>
+hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, bool persistent,
+                       const Workspace& ws, int64_t ld, hipStream_t s) {
+    switch (chunk) {
+        case 64: return launch_tiled_one<P, TS, 64>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 128: return launch_tiled_one<P, TS, 128>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 256: return launch_tiled_one<P, TS, 256>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 512: return launch_tiled_one<P, TS, 512>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 1024: return launch_tiled_one<P, TS, 1024>(ix, qb, q0, qt, persistent, ws, ld, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -478,7 +572,8 @@ hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s)
 }
 
 hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s) {
-    hipError_t e = fill_u32(ws.hist1, (int64_t)qt * kHistBins, s);
+    hipError_t e = fill_u32(ws.counters, 8, s);
+    if (e == hipSuccess) e = fill_u32(ws.hist1, (int64_t)qt * kHistBins, s);
     if (e == hipSuccess) e = fill_u32(ws.hist_ref, (int64_t)qt * kHistBins, s);
     if (e == hipSuccess) e = fill_u32(ws.state, (int64_t)qt * sizeof(SelState) / 4, s);
     return e;
@@ -489,12 +584,12 @@ hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0
     const int64_t ld = score_ld(ix.n_docs);
     return by_precision(ix.precision, [&](auto pc) -> hipError_t {
         constexpr int P = decltype(pc)::value;
-        const int order = o.kernel == 4 ? 1 : 0;  // GS_KERNEL_SHARED: tile-major, XCD-aware
+        const bool persistent = o.kernel == 4;  // GS_KERNEL_SHARED: persistent, tile-major, XCD-aware
         switch (o.tile_shift) {
-            case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, order, ws, ld, s);
-            case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, order, ws, ld, s);
+            case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
+            case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
             case 15:
-                if constexpr (P == kU8) return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, order, ws, ld, s);
+                if constexpr (P == kU8) return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
                 return hipErrorInvalidValue;  // 32768 fixed-point accumulators exceed one CU's LDS
         }
         return hipErrorInvalidValue;

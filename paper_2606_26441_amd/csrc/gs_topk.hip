@@ -216,14 +216,14 @@ __device__ void rank_band(const double* bs, const int32_t* bid, int nb, int64_t 
 }
 
 // Band of the bf16 form. Every doc's approximate score satisfies
-//   s(1-delta) <= approx <= s(1+delta) + E
+//   s(1-delta) - E <= approx <= s(1+delta) + E
 // (delta: relative error of the stored bf16 weights and of the fp32 score; E:
-// the fixed-point excess, products round up, so approx = 0 exactly when s = 0).
-// Then approx_k <= (1+delta) s_k + E, and every true top-k doc has
-//   approx >= s(1-delta) >= s_k(1-delta) >= (approx_k - E)(1-delta)/(1+delta) = tau.
+// the fixed-point error bound; a positive product never rounds to 0, so
+// approx = 0 exactly when s = 0). Then approx_k <= (1+delta) s_k + E, and every
+// true top-k doc has approx >= s(1-delta) - E >= (approx_k - E)(1-delta)/(1+delta) - E = tau.
 __device__ __forceinline__ double band_tau(float sk, float delta, double abs_err) {
     const double d = (double)delta;
-    const double t = ((double)sk - abs_err) * (1.0 - d) / (1.0 + d);
+    const double t = ((double)sk - abs_err) * (1.0 - d) / (1.0 + d) - abs_err;
     return t > 0.0 ? t * (1.0 - 1e-12) : 0.0;
 }
 
