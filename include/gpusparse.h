@@ -177,6 +177,28 @@ int32_t gs_batch_create(gs_index index, const int64_t* q_row_ptr, int32_t n_quer
 void gs_batch_free(gs_batch batch);
 
 /*
+ * A batch with fixed capacity, for reuse across searches (hipGraph replays,
+ * serving slots): room for max_queries queries holding max_nnz terms in total,
+ * k <= k_max. Until filled, every slot is an empty query with k = 0.
+ * Errors: GS_EINVAL, GS_ENOMEM, GS_EHIP.
+ */
+int32_t gs_batch_reserve(gs_index index, int32_t max_queries, int64_t max_nnz, int32_t k_max,
+                         gs_batch* out);
+
+/*
+ * Replace the queries of a batch in place (same rules as gs_batch_create),
+ * n_queries <= capacity, q_nnz <= capacity. Slots n_queries..capacity-1 become
+ * empty queries with k = 0: no scoring work, their result rows are padding.
+ * Waits for work already enqueued on hip_stream (which may read the batch),
+ * then copies synchronously. Launch shapes depend only on the capacity, so a
+ * graph made by gs_graph_create keeps working after an update.
+ * Errors: GS_EINVAL (nothing is changed), GS_EHIP.
+ */
+int32_t gs_batch_update(gs_batch batch, const int64_t* q_row_ptr, int32_t n_queries,
+                        const int32_t* q_term_ids, const float* q_weights, int64_t q_nnz,
+                        const int32_t* k, void* hip_stream);
+
+/*
  * Device workspace (bytes) needed to search query_tile queries at once with
  * these options (opts may be NULL). It holds one score array of n_docs 32-bit
  * words per live query plus selection scratch.
@@ -210,6 +232,22 @@ int32_t gs_search(gs_index index, const int64_t* q_row_ptr, int32_t n_queries,
                   const int32_t* k, int32_t k_max, void* workspace, size_t workspace_bytes,
                   int32_t* out_ids, void* out_scores, const gs_search_opts* opts,
                   void* hip_stream);
+
+/*
+ * hipGraph form of gs_search_batch: the full launch sequence for this batch
+ * (at its capacity), workspace and outputs is run once on hip_stream and then
+ * captured into a graph; gs_graph_launch replays it on any stream. The graph
+ * holds the pointers given here: they must stay valid, and the batch may be
+ * refilled with gs_batch_update between launches. No memset or host work is
+ * captured (buffers are cleared by kernels). Errors: as gs_search_batch, plus
+ * GS_EHIP for capture or instantiation failures.
+ */
+typedef struct gs_graph_s* gs_graph;
+int32_t gs_graph_create(gs_index index, gs_batch batch, void* workspace, size_t workspace_bytes,
+                        int32_t* out_ids, void* out_scores, const gs_search_opts* opts,
+                        void* hip_stream, gs_graph* out);
+int32_t gs_graph_launch(gs_graph graph, void* hip_stream);
+void gs_graph_free(gs_graph graph);
 
 /*
  * Per-query selection diagnostics of the last gs_search_batch on this batch

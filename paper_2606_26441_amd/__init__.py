@@ -75,6 +75,16 @@ def _load() -> ctypes.CDLL:
     lib.gs_batch_create.restype = i32
     lib.gs_batch_free.argtypes = [vp]
     lib.gs_batch_free.restype = None
+    lib.gs_batch_reserve.argtypes = [vp, i32, i64, i32, P(vp)]
+    lib.gs_batch_reserve.restype = i32
+    lib.gs_batch_update.argtypes = [vp, vp, i32, vp, vp, i64, vp, vp]
+    lib.gs_batch_update.restype = i32
+    lib.gs_graph_create.argtypes = [vp, vp, vp, sz, vp, vp, P(SearchOpts), vp, P(vp)]
+    lib.gs_graph_create.restype = i32
+    lib.gs_graph_launch.argtypes = [vp, vp]
+    lib.gs_graph_launch.restype = i32
+    lib.gs_graph_free.argtypes = [vp]
+    lib.gs_graph_free.restype = None
     lib.gs_workspace_size.argtypes = [vp, i32, P(SearchOpts), P(sz)]
     lib.gs_workspace_size.restype = i32
     lib.gs_search_batch.argtypes = [vp, vp, vp, sz, vp, vp, P(SearchOpts), vp]
@@ -223,7 +233,7 @@ class Index:
 
 
 class Batch:
-    """A validated query batch resident on the device."""
+    """A validated query batch resident on the device (capacity = its query count unless reserved)."""
 
     def __init__(self, index: Index, row_ptr, terms, weights, k, k_max=None, stream=None):
         rp, t, w = _np(row_ptr, np.int64), _np(terms, np.int32), _np(weights, np.float32)
@@ -239,6 +249,27 @@ class Batch:
         self._h = h
         self._index = index
 
+    @classmethod
+    def reserve(cls, index: Index, max_queries: int, max_nnz: int, k_max: int) -> "Batch":
+        self = cls.__new__(cls)
+        h = ctypes.c_void_p()
+        _check(lib.gs_batch_reserve(index.handle, int(max_queries), int(max_nnz), int(k_max), ctypes.byref(h)),
+               "gs_batch_reserve")
+        self._h, self._index = h, index
+        self.n_queries, self.k_max = int(max_queries), int(k_max)
+        self.k = np.zeros(self.n_queries, np.int32)
+        return self
+
+    def update(self, queries, k, stream=None):
+        """Refill in place (at most the reserved capacity); unused slots become empty queries with k = 0."""
+        rp, t, w = _np(queries.row_ptr, np.int64), _np(queries.terms, np.int32), _np(queries.weights, np.float32)
+        nq = rp.shape[0] - 1
+        kk = np.broadcast_to(np.asarray(k, dtype=np.int32), (nq,)).copy()
+        _check(lib.gs_batch_update(self._h, rp.ctypes.data, nq, t.ctypes.data, w.ctypes.data, t.shape[0],
+                                   kk.ctypes.data, _stream_ptr(stream)), "gs_batch_update")
+        self.k = np.zeros(self.n_queries, np.int32)
+        self.k[:nq] = kk
+
     @property
     def handle(self):
         return self._h
@@ -252,6 +283,33 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             lib.gs_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured search (hipGraph) bound to an index, a batch, a workspace and output tensors."""
+
+    def __init__(self, index: Index, batch: Batch, workspace: torch.Tensor, ids: torch.Tensor, scores: torch.Tensor,
+                 opts: Optional[SearchOpts] = None, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib.gs_graph_create(index.handle, batch.handle, workspace.data_ptr(), workspace.numel(),
+                                   ids.data_ptr(), scores.data_ptr(), ctypes.byref(opts) if opts else None,
+                                   _stream_ptr(stream), ctypes.byref(h)), "gs_graph_create")
+        self._h = h
+        self._keep = (index, batch, workspace, ids, scores)
+
+    def launch(self, stream=None):
+        _check(lib.gs_graph_launch(self._h, _stream_ptr(stream)), "gs_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.gs_graph_free(self._h)
             self._h = None
 
     def __del__(self):

@@ -301,8 +301,9 @@ struct gs_index_s {
 
 struct gs_batch_s {
     gs_index index = nullptr;
-    int32_t n_queries = 0, k_max = 0;
-    int64_t q_nnz = 0;
+    int32_t n_queries = 0, k_max = 0;  // capacity in queries (launch shapes use it)
+    int64_t q_nnz = 0;                 // capacity in query terms
+    int32_t n_active = 0;              // queries set by the last update
     std::vector<void*> allocs;
     DevBatch dev{};
     int32_t* diag = nullptr;  // [n_queries * 4]
@@ -357,7 +358,7 @@ struct SpanRecorder {
     TimedSpan span{};
     bool active = false;
     SpanRecorder(int kind, hipStream_t s) {
-        if (!timing_on()) return;
+        if (kind < 0 || !timing_on()) return;
         span.kind = kind;
         if (hipEventCreate(&span.a) != hipSuccess) return;
         if (hipEventCreate(&span.b) != hipSuccess) {
@@ -587,41 +588,90 @@ void gs_free_index(gs_index ix) {
     delete ix;
 }
 
-int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
-                        const float* q_weights, int64_t q_nnz, const int32_t* k, int32_t k_max, void* hip_stream,
-                        gs_batch* out) {
+int32_t gs_batch_reserve(gs_index ix, int32_t max_queries, int64_t max_nnz, int32_t k_max, gs_batch* out) {
     g_err.clear();
     if (!out) return fail(GS_EINVAL, "out is null");
     *out = nullptr;
     if (!ix) return fail(GS_EINVAL, "index is null");
-    if (n_queries < 0) return fail(GS_EINVAL, "n_queries < 0");
+    if (max_queries < 0 || max_nnz < 0) return fail(GS_EINVAL, "negative capacity");
     if (k_max < 0 || k_max > GS_MAX_K) return fail(GS_EINVAL, "k_max must be in [0, GS_MAX_K]");
-    if (n_queries > 0 && !k) return fail(GS_EINVAL, "k is null");
-    for (int32_t q = 0; q < n_queries; q++)
-        if (k[q] < 0 || k[q] > k_max) return fail(GS_EINVAL, "k[" + std::to_string(q) + "] outside [0, k_max]");
-    Rows r{q_row_ptr, q_term_ids, q_weights, n_queries, {}, {}};
-    int32_t rc = check_rows(r, q_nnz, ix->vocab, kMaxQueryNnz, "queries");
-    if (rc != GS_OK) return rc;
     DeviceGuard g(ix->device);
-    hipStream_t s = (hipStream_t)hip_stream;
     gs_batch b = new (std::nothrow) gs_batch_s();
     if (!b) return fail(GS_ENOMEM, "host allocation failed");
     b->index = ix;
-    b->n_queries = n_queries;
+    b->n_queries = max_queries;
     b->k_max = k_max;
-    b->q_nnz = q_nnz;
+    b->q_nnz = max_nnz;
     auto done = [&](int32_t code) {
         if (code != GS_OK) delete b;
         return code;
     };
-    std::vector<int64_t> rp(q_row_ptr ? q_row_ptr : nullptr, q_row_ptr ? q_row_ptr + n_queries + 1 : nullptr);
-    if (rp.empty()) rp.push_back(0);
-    std::vector<int32_t> w8((size_t)q_nnz), fshift((size_t)n_queries);
-    std::vector<double> qfx((size_t)q_nnz);
-    std::vector<float> delta((size_t)n_queries);
-    std::vector<double> qscale((size_t)n_queries), qerr((size_t)n_queries);
-    std::vector<int64_t> qwork((size_t)n_queries, 0);
-    for (int32_t q = 0; q < n_queries; q++) {
+    const size_t nq = (size_t)max_queries, nz = (size_t)max_nnz;
+    size_t bytes = 0;
+    int32_t rc;
+    DevBatch& d = b->dev;
+    int64_t *rp = nullptr, *work = nullptr;
+    int32_t *t = nullptr, *w8 = nullptr, *k = nullptr, *fs = nullptr;
+    float *w = nullptr, *delta = nullptr;
+    double *fx = nullptr, *scale = nullptr, *err = nullptr;
+    if ((rc = dev_upload<int64_t>(b->allocs, bytes, nullptr, nq + 1, &rp, nullptr))) return done(rc);
+    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nz, &t, nullptr))) return done(rc);
+    if ((rc = dev_upload<float>(b->allocs, bytes, nullptr, nz, &w, nullptr))) return done(rc);
+    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nz, &w8, nullptr))) return done(rc);
+    if ((rc = dev_upload<double>(b->allocs, bytes, nullptr, nz, &fx, nullptr))) return done(rc);
+    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nq, &k, nullptr))) return done(rc);
+    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nq, &fs, nullptr))) return done(rc);
+    if ((rc = dev_upload<float>(b->allocs, bytes, nullptr, nq, &delta, nullptr))) return done(rc);
+    if ((rc = dev_upload<double>(b->allocs, bytes, nullptr, nq, &scale, nullptr))) return done(rc);
+    if ((rc = dev_upload<double>(b->allocs, bytes, nullptr, nq, &err, nullptr))) return done(rc);
+    if ((rc = dev_upload<int64_t>(b->allocs, bytes, nullptr, nq, &work, nullptr))) return done(rc);
+    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nq * 4, &b->diag, nullptr))) return done(rc);
+    d.n_queries = max_queries;
+    d.k_max = k_max;
+    d.q_row_ptr = rp;
+    d.q_term = t;
+    d.q_w = w;
+    d.q_w8 = w8;
+    d.q_fx = fx;
+    d.k = k;
+    d.first_shift = fs;
+    d.delta = delta;
+    d.q_scale = scale;
+    d.q_abs_err = err;
+    d.q_work = work;
+    // an empty batch until the first update: every slot is a query with no terms and k = 0
+    std::vector<int64_t> zero_rp(nq + 1, 0);
+    int32_t rc2 = gs_batch_update(b, zero_rp.data(), 0, nullptr, nullptr, 0, nullptr, nullptr);
+    if (rc2 != GS_OK) return done(rc2);
+    *out = b;
+    return GS_OK;
+}
+
+int32_t gs_batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
+                        const float* q_weights, int64_t q_nnz, const int32_t* k, void* hip_stream) {
+    g_err.clear();
+    if (!b) return fail(GS_EINVAL, "batch is null");
+    gs_index ix = b->index;
+    if (n_queries < 0 || n_queries > b->n_queries)
+        return fail(GS_EINVAL, "n_queries outside [0, batch capacity]");
+    if (q_nnz < 0 || q_nnz > b->q_nnz) return fail(GS_EINVAL, "q_nnz exceeds the batch capacity");
+    if (n_queries > 0 && !k) return fail(GS_EINVAL, "k is null");
+    for (int32_t q = 0; q < n_queries; q++)
+        if (k[q] < 0 || k[q] > b->k_max) return fail(GS_EINVAL, "k[" + std::to_string(q) + "] outside [0, k_max]");
+    Rows r{q_row_ptr, q_term_ids, q_weights, n_queries, {}, {}};
+    int32_t rc = check_rows(r, q_nnz, ix->vocab, kMaxQueryNnz, "queries");
+    if (rc != GS_OK) return rc;
+    const int32_t cap = b->n_queries;
+    // slots past n_queries become empty queries with k = 0 (no work, padding-only rows)
+    std::vector<int64_t> rp((size_t)cap + 1, q_nnz);
+    for (int32_t q = 0; q <= n_queries; q++) rp[(size_t)q] = q_row_ptr ? q_row_ptr[q] : 0;
+    std::vector<int32_t> kk((size_t)cap, 0), w8((size_t)std::max<int64_t>(q_nnz, 1), 0), fshift((size_t)cap);
+    for (int32_t q = 0; q < n_queries; q++) kk[(size_t)q] = k[q];
+    std::vector<double> qfx((size_t)std::max<int64_t>(q_nnz, 1), 0.0);
+    std::vector<float> delta((size_t)cap);
+    std::vector<double> qscale((size_t)cap), qerr((size_t)cap);
+    std::vector<int64_t> qwork((size_t)cap, 0);
+    for (int32_t q = 0; q < cap; q++) {
         uint64_t maxs = 0;
         double maxprod = 0.0;
         const int64_t m = rp[(size_t)q + 1] - rp[(size_t)q];
@@ -650,41 +700,46 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
         // bf16 form: relative error of a stored weight (2^-8) and of the fp32 score (2^-24, with margin)
         delta[(size_t)q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -23)) - 1.0) * (1.0 + 1e-6));
     }
-    int64_t* d_rp = nullptr;
-    int32_t *d_t = nullptr, *d_w8 = nullptr, *d_k = nullptr, *d_fs = nullptr;
-    float *d_w = nullptr, *d_delta = nullptr;
-    size_t bytes = 0;
-    if ((rc = dev_upload(b->allocs, bytes, rp.data(), rp.size(), &d_rp, s))) return done(rc);
-    if ((rc = dev_upload(b->allocs, bytes, r.term, (size_t)q_nnz, &d_t, s))) return done(rc);
-    if ((rc = dev_upload(b->allocs, bytes, r.w, (size_t)q_nnz, &d_w, s))) return done(rc);
-    if ((rc = dev_upload(b->allocs, bytes, w8.data(), w8.size(), &d_w8, s))) return done(rc);
-    if ((rc = dev_upload(b->allocs, bytes, k, (size_t)n_queries, &d_k, s))) return done(rc);
-    if ((rc = dev_upload(b->allocs, bytes, fshift.data(), fshift.size(), &d_fs, s))) return done(rc);
-    if ((rc = dev_upload(b->allocs, bytes, delta.data(), delta.size(), &d_delta, s))) return done(rc);
-    double *d_qfx = nullptr, *d_qscale = nullptr, *d_qerr = nullptr;
-    if ((rc = dev_upload(b->allocs, bytes, qfx.data(), qfx.size(), &d_qfx, s))) return done(rc);
-    if ((rc = dev_upload(b->allocs, bytes, qscale.data(), qscale.size(), &d_qscale, s))) return done(rc);
-    if ((rc = dev_upload(b->allocs, bytes, qerr.data(), qerr.size(), &d_qerr, s))) return done(rc);
-    int64_t* d_qwork = nullptr;
-    if ((rc = dev_upload(b->allocs, bytes, qwork.data(), qwork.size(), &d_qwork, s))) return done(rc);
-    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, (size_t)n_queries * 4, &b->diag, s))) return done(rc);
-    hipError_t e = hipMemsetAsync(b->diag, 0, (size_t)std::max(n_queries, 1) * 16, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return done(fail(GS_EHIP, std::string("batch upload: ") + hipGetErrorString(e)));
-    DevBatch& d = b->dev;
-    d.n_queries = n_queries;
-    d.k_max = k_max;
-    d.q_row_ptr = d_rp;
-    d.q_term = d_t;
-    d.q_w = d_w;
-    d.q_w8 = d_w8;
-    d.k = d_k;
-    d.first_shift = d_fs;
-    d.delta = d_delta;
-    d.q_fx = d_qfx;
-    d.q_scale = d_qscale;
-    d.q_abs_err = d_qerr;
-    d.q_work = d_qwork;
+    DeviceGuard g(ix->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    // searches already enqueued on this stream may still read the batch
+    GS_HIP(hipStreamSynchronize(s));
+    const DevBatch& d = b->dev;
+    auto up = [&](const void* dst, const void* src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpy((void*)dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    hipError_t e = up(d.q_row_ptr, rp.data(), rp.size() * 8);
+    if (e == hipSuccess) e = up(d.q_term, r.term, (size_t)q_nnz * 4);
+    if (e == hipSuccess) e = up(d.q_w, r.w, (size_t)q_nnz * 4);
+    if (e == hipSuccess) e = up(d.q_w8, w8.data(), (size_t)q_nnz * 4);
+    if (e == hipSuccess) e = up(d.q_fx, qfx.data(), (size_t)q_nnz * 8);
+    if (e == hipSuccess) e = up(d.k, kk.data(), (size_t)cap * 4);
+    if (e == hipSuccess) e = up(d.first_shift, fshift.data(), (size_t)cap * 4);
+    if (e == hipSuccess) e = up(d.delta, delta.data(), (size_t)cap * 4);
+    if (e == hipSuccess) e = up(d.q_scale, qscale.data(), (size_t)cap * 8);
+    if (e == hipSuccess) e = up(d.q_abs_err, qerr.data(), (size_t)cap * 8);
+    if (e == hipSuccess) e = up(d.q_work, qwork.data(), (size_t)cap * 8);
+    if (e == hipSuccess) e = hipMemset(b->diag, 0, (size_t)std::max(cap, 1) * 16);
+    if (e != hipSuccess) return fail(GS_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
+    b->n_active = n_queries;
+    return GS_OK;
+}
+
+int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
+                        const float* q_weights, int64_t q_nnz, const int32_t* k, int32_t k_max, void* hip_stream,
+                        gs_batch* out) {
+    g_err.clear();
+    if (!out) return fail(GS_EINVAL, "out is null");
+    *out = nullptr;
+    if (n_queries < 0 || q_nnz < 0) return fail(GS_EINVAL, "negative size");
+    gs_batch b = nullptr;
+    int32_t rc = gs_batch_reserve(ix, n_queries, q_nnz, k_max, &b);
+    if (rc != GS_OK) return rc;
+    rc = gs_batch_update(b, q_row_ptr, n_queries, q_term_ids, q_weights, q_nnz, k, hip_stream);
+    if (rc != GS_OK) {
+        gs_batch_free(b);
+        return rc;
+    }
     *out = b;
     return GS_OK;
 }
@@ -739,32 +794,34 @@ int32_t gs_workspace_size(gs_index ix, int32_t query_tile, const gs_search_opts*
     return GS_OK;
 }
 
-int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspace_bytes_, int32_t* out_ids,
-                        void* out_scores, const gs_search_opts* opts, void* hip_stream) {
-    g_err.clear();
+}  // extern "C"
+
+namespace {
+
+// Validate a search request and pick the query-tile size the workspace allows.
+int32_t plan_search(gs_index ix, gs_batch b, size_t workspace_bytes_, const gs_search_opts* opts, ScoreOpts* so,
+                    int32_t* qt) {
     if (!ix || !b) return fail(GS_EINVAL, "null index or batch");
     if (b->index != ix) return fail(GS_EINVAL, "batch was created for another index");
-    ScoreOpts so;
-    int32_t rc = resolve_opts(ix, opts, &so);
+    int32_t rc = resolve_opts(ix, opts, so);
     if (rc != GS_OK) return rc;
-    const int32_t nq = b->n_queries;
-    if (nq == 0 || b->k_max == 0) return GS_OK;
-    if (!out_ids || !out_scores) return fail(GS_EINVAL, "null output");
-    if (!workspace) return fail(GS_EINVAL, "null workspace");
-    int32_t qt = 1;
     if (workspace_bytes(ix->n_docs, 1, ix->precision) > workspace_bytes_)
         return fail(GS_ECAPACITY, "workspace smaller than gs_workspace_size(index, 1)");
-    {
-        int32_t lo = 1, hi = nq;
-        while (lo < hi) {
-            const int32_t mid = lo + (hi - lo + 1) / 2;
-            if (workspace_bytes(ix->n_docs, mid, ix->precision) <= workspace_bytes_) lo = mid; else hi = mid - 1;
-        }
-        qt = lo;
+    const int32_t nq = std::max(b->n_queries, 1);
+    int32_t lo = 1, hi = nq;
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo + 1) / 2;
+        if (workspace_bytes(ix->n_docs, mid, ix->precision) <= workspace_bytes_) lo = mid; else hi = mid - 1;
     }
-    if (opts && opts->query_tile > 0) qt = std::min(qt, opts->query_tile);
-    DeviceGuard g(ix->device);
-    hipStream_t s = (hipStream_t)hip_stream;
+    *qt = lo;
+    if (opts && opts->query_tile > 0) *qt = std::min(*qt, opts->query_tile);
+    return GS_OK;
+}
+
+// Enqueue the whole search on stream s (no host synchronisation; capturable).
+int32_t enqueue_search(gs_index ix, gs_batch b, void* workspace, int32_t qt, const ScoreOpts& so, int32_t* out_ids,
+                       void* out_scores, hipStream_t s, bool timing) {
+    const int32_t nq = b->n_queries;
     Workspace ws;
     carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
     (void)hipGetLastError();  // launches below report their own status; drop any earlier, unrelated one
@@ -773,14 +830,14 @@ int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspa
         const int32_t n = std::min(qt, nq - q0);
         hipError_t e = launch_clear(ws, n, s);
         if (e == hipSuccess && ix->n_docs > 0) {
-            SpanRecorder rec(0, s);
+            SpanRecorder rec(timing ? 0 : -1, s);
             if (so.kernel == GS_KERNEL_ATOMIC) e = launch_score_atomic(ix->dev, b->dev, q0, n, so, ws, s);
             else if (so.kernel == GS_KERNEL_DOCPAR) e = launch_score_docpar(ix->dev, b->dev, q0, n, so, ws, s);
             else e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s);
             rec.end(s);
         }
         if (e == hipSuccess) {
-            SpanRecorder rec(1, s);
+            SpanRecorder rec(timing ? 1 : -1, s);
             e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s);
             rec.end(s);
         }
@@ -788,6 +845,93 @@ int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspa
             return fail(GS_EHIP, std::string("launch of ") + g_failed_launch + ": " + hipGetErrorString(e));
     }
     return GS_OK;
+}
+
+}  // namespace
+
+struct gs_graph_s {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~gs_graph_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+extern "C" {
+
+int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspace_bytes_, int32_t* out_ids,
+                        void* out_scores, const gs_search_opts* opts, void* hip_stream) {
+    g_err.clear();
+    ScoreOpts so;
+    int32_t qt = 1;
+    int32_t rc = plan_search(ix, b, workspace_bytes_, opts, &so, &qt);
+    if (rc != GS_OK) return rc;
+    if (b->n_queries == 0 || b->k_max == 0) return GS_OK;
+    if (!out_ids || !out_scores) return fail(GS_EINVAL, "null output");
+    if (!workspace) return fail(GS_EINVAL, "null workspace");
+    DeviceGuard g(ix->device);
+    return enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, (hipStream_t)hip_stream, true);
+}
+
+int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspace_bytes_, int32_t* out_ids,
+                        void* out_scores, const gs_search_opts* opts, void* hip_stream, gs_graph* out) {
+    g_err.clear();
+    if (!out) return fail(GS_EINVAL, "out is null");
+    *out = nullptr;
+    ScoreOpts so;
+    int32_t qt = 1;
+    int32_t rc = plan_search(ix, b, workspace_bytes_, opts, &so, &qt);
+    if (rc != GS_OK) return rc;
+    if (b->n_queries == 0 || b->k_max == 0) return fail(GS_EINVAL, "empty batch");
+    if (!out_ids || !out_scores || !workspace) return fail(GS_EINVAL, "null workspace or output");
+    DeviceGuard g(ix->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    // one eager run first: one-time kernel attributes and occupancy queries happen outside the capture
+    rc = enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, s, false);
+    if (rc != GS_OK) return rc;
+    GS_HIP(hipStreamSynchronize(s));
+    gs_graph gr = new (std::nothrow) gs_graph_s();
+    if (!gr) return fail(GS_ENOMEM, "host allocation failed");
+    gr->device = ix->device;
+    // capture on a private stream (the legacy default stream cannot be captured)
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        if (cs) (void)hipStreamDestroy(cs);
+        delete gr;
+        return fail(GS_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    rc = enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, cs, false);
+    e = hipStreamEndCapture(cs, &gr->graph);
+    (void)hipStreamDestroy(cs);
+    if (rc != GS_OK) {
+        delete gr;
+        return rc;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        delete gr;
+        return fail(GS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *out = gr;
+    return GS_OK;
+}
+
+int32_t gs_graph_launch(gs_graph gr, void* hip_stream) {
+    g_err.clear();
+    if (!gr) return fail(GS_EINVAL, "graph is null");
+    DeviceGuard g(gr->device);
+    GS_HIP(hipGraphLaunch(gr->exec, (hipStream_t)hip_stream));
+    return GS_OK;
+}
+
+void gs_graph_free(gs_graph gr) {
+    if (!gr) return;
+    DeviceGuard g(gr->device);
+    delete gr;
 }
 
 int32_t gs_search(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
