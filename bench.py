@@ -53,6 +53,9 @@ def parse():
                     help="other precision[:kernel] forms to time (comma list, or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16, help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--profile", action="store_true", help="main form only, no CPU leg (for profiler runs)")
+    ap.add_argument("--batched", default="u8,bf16",
+                    help="precisions for the 4,096-query uneven batch (autotuned, graph vs plain), or 'none'")
+    ap.add_argument("--batched-queries", type=int, default=4096)
     return ap.parse_args()
 
 
@@ -112,6 +115,114 @@ def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_
     batch.close()
     idx.close()
     torch.cuda.empty_cache()
+    return res
+
+
+def run_batched(gs, torch, docs, args):
+    """Uneven batch: lognormal query lengths (median 25, 5..250), k mixed over {10, 100, 1000}; autotuned
+    options; one persistent-or-grid launch per step; hipGraph replay vs plain launches; oracle-checked sample."""
+    import workload
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity_rules import check_exact_f64, check_exact_int
+
+    w = workload.WORKLOADS["uneven-8.8m"]
+    nq = args.batched_queries
+    queries = workload.make_queries(w, n=nq)
+    k = workload.k_mix(nq, seed=4)
+    res = {"workload": w.name, "queries": nq, "query_nnz_mean": round(queries.nnz / nq, 2),
+           "query_nnz_max": int(np.diff(queries.row_ptr).max()), "k_mix": [10, 100, 1000]}
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    for prec in [p for p in args.batched.split(",") if p]:
+        log("batched %s: index + autotune ..." % prec)
+        idx = gs.Index.from_rows(docs, prec)
+        tune_q = queries.subset(np.arange(min(512, nq)))
+        tb = idx.batch(tune_q, k[: tune_q.n_rows], k_max=1000)
+        best, table = idx.autotune(tb, reps=1)
+        tb.close()
+        opts = gs.make_opts(best.kernel, tile_docs=best.tile_docs, chunk=best.chunk)
+        batch = idx.batch(queries, k, k_max=1000)
+        ws = idx.workspace(nq, opts)
+        ids = torch.empty((nq, 1000), dtype=torch.int32, device="cuda")
+        sc = torch.empty((nq, 1000), dtype=gs.SCORE_DTYPES[idx.precision], device="cuda")
+        idx.search(batch, ws, opts, out=(ids, sc))
+        torch.cuda.synchronize()
+        steps = 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            idx.search(batch, ws, opts, out=(ids, sc))
+        e1.record()
+        torch.cuda.synchronize()
+        plain_ms = e0.elapsed_time(e1) / steps
+        graph = gs.Graph(idx, batch, ws, ids, sc, opts)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            graph.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / steps
+        diag = batch.diagnostics()
+        got_ids, got_sc = ids.cpu().numpy(), sc.cpu().numpy()
+        graph.close()
+        del ws
+        # small batch (16 queries): where launch overhead matters
+        small = queries.subset(np.arange(16))
+        sb = idx.batch(small, k[:16], k_max=1000)
+        sws = idx.workspace(16, opts)
+        sids = torch.empty((16, 1000), dtype=torch.int32, device="cuda")
+        ssc = torch.empty((16, 1000), dtype=gs.SCORE_DTYPES[idx.precision], device="cuda")
+        idx.search(sb, sws, opts, out=(sids, ssc))
+        g16 = gs.Graph(idx, sb, sws, sids, ssc, opts)
+        torch.cuda.synchronize()
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            idx.search(sb, sws, opts, out=(sids, ssc))
+        e1.record()
+        torch.cuda.synchronize()
+        small_plain = e0.elapsed_time(e1) / reps
+        e0.record()
+        for _ in range(reps):
+            g16.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        small_graph = e0.elapsed_time(e1) / reps
+        g16.close()
+        # oracle-checked sample of the large batch
+        s = 4
+        sample = queries.subset(np.arange(s))
+        status = "ok"
+        try:
+            if prec == "u8":
+                rid, rsc = oracle.topk_i64(docs, sample, k[:s], k_max=1000, n_threads=threads)
+                for q in range(s):
+                    check_exact_int(got_ids[q], got_sc[q], rid[q], rsc[q], what="batched u8")
+            else:
+                rid, rsc = oracle.topk_f64(docs, sample, k[:s], k_max=1000, n_threads=threads)
+                for q in range(s):
+                    check_exact_f64(got_ids[q], got_sc[q], rid[q], rsc[q], what="batched bf16")
+            status = "exact on %d sampled queries" % s
+        except AssertionError as e:
+            status = "MISMATCH: " + str(e)[:160]
+        names = {1: "tiled", 4: "shared"}
+        res[prec] = {"qps_plain": round(nq / (plain_ms / 1e3), 1), "qps_graph": round(nq / (graph_ms / 1e3), 1),
+                     "ms_plain": round(plain_ms, 3), "ms_graph": round(graph_ms, 3),
+                     "small_batch_16": {"ms_plain": round(small_plain, 3), "ms_graph": round(small_graph, 3)},
+                     "tuned": {"kernel": names.get(best.kernel, best.kernel), "tile_docs": best.tile_docs,
+                               "chunk": best.chunk},
+                     "tuning_table_ms": [[names.get(c["kernel"], c["kernel"]), c["tile_docs"], c["chunk"],
+                                          round(t, 2)] for c, t in table],
+                     "overflow": int(diag[:, 3].max()), "parity": status}
+        log("batched %s: plain %.1f QPS, graph %.1f QPS, tuned %s; %s" % (prec, res[prec]["qps_plain"],
+                                                                         res[prec]["qps_graph"], res[prec]["tuned"],
+                                                                         status))
+        sb.close()
+        batch.close()
+        idx.close()
+        del sws, ids, sc, sids, ssc
+        torch.cuda.empty_cache()
     return res
 
 
@@ -266,6 +377,8 @@ def main():
             checked["error"] = str(e)[:200]
         out["parity_sample"] = checked
         log("parity: %s" % checked)
+    if not args.profile and args.batched != "none":
+        out["batched"] = run_batched(gs, torch, docs, args)
     for f in forms.values():
         f.pop("_res", None)
     if forms:

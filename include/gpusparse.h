@@ -250,6 +250,20 @@ int32_t gs_graph_launch(gs_graph graph, void* hip_stream);
 void gs_graph_free(gs_graph graph);
 
 /*
+ * Autotuner: runs this batch with every candidate option set - scoring kernel
+ * (GS_KERNEL_TILED, GS_KERNEL_SHARED) x tile_docs (8192, 16384; plus 32768 for
+ * GS_U8) x chunk (128, 256, 512, 1024) - one untimed run then `reps` timed runs
+ * each (HIP events on hip_stream), and writes the fastest option set to *best.
+ * Optional host outputs: cands[max_candidates] (the option sets tried, in
+ * order), times_ms[max_candidates] (mean search time of each), n_candidates.
+ * Synchronous; overwrites out_ids / out_scores. Errors: as gs_search_batch.
+ */
+int32_t gs_autotune(gs_index index, gs_batch batch, void* workspace, size_t workspace_bytes,
+                    int32_t* out_ids, void* out_scores, int32_t reps, void* hip_stream,
+                    gs_search_opts* best, gs_search_opts* cands, float* times_ms,
+                    int32_t max_candidates, int32_t* n_candidates);
+
+/*
  * Per-query selection diagnostics of the last gs_search_batch on this batch
  * (host copy; call after the stream has been synchronised).
  * out [n_queries * 4] int32: candidates kept by the filter, refinement passes

@@ -85,6 +85,8 @@ def _load() -> ctypes.CDLL:
     lib.gs_graph_launch.restype = i32
     lib.gs_graph_free.argtypes = [vp]
     lib.gs_graph_free.restype = None
+    lib.gs_autotune.argtypes = [vp, vp, vp, sz, vp, vp, i32, vp, P(SearchOpts), vp, vp, i32, P(i32)]
+    lib.gs_autotune.restype = i32
     lib.gs_workspace_size.argtypes = [vp, i32, P(SearchOpts), P(sz)]
     lib.gs_workspace_size.restype = i32
     lib.gs_search_batch.argtypes = [vp, vp, vp, sz, vp, vp, P(SearchOpts), vp]
@@ -103,6 +105,7 @@ def _load() -> ctypes.CDLL:
 
 
 lib = _load()
+_TUNED = {}  # (n_docs, precision, n_queries) -> (best SearchOpts, timing table)
 
 
 def _check(rc: int, where: str):
@@ -219,6 +222,30 @@ class Index:
                              k_max, workspace.data_ptr(), workspace.numel(), ids.data_ptr(), scores.data_ptr(),
                              ctypes.byref(opts) if opts else None, _stream_ptr(stream)), "gs_search")
         return ids, scores
+
+    def autotune(self, batch: "Batch", workspace: Optional[torch.Tensor] = None, reps: int = 2, stream=None):
+        """Time every candidate option set on this batch; returns (best SearchOpts, [(opts dict, ms), ...]).
+
+        Results are cached per (collection size, precision, batch size) for the life of the process.
+        """
+        key = (self.n_docs, self.precision, batch.n_queries)
+        if key in _TUNED:
+            return _TUNED[key]
+        if workspace is None:
+            workspace = self.workspace(batch.n_queries)
+        ids = torch.empty((batch.n_queries, batch.k_max), dtype=torch.int32, device=workspace.device)
+        sc = torch.empty((batch.n_queries, batch.k_max), dtype=SCORE_DTYPES[self.precision], device=workspace.device)
+        best = SearchOpts()
+        cands = (SearchOpts * 64)()
+        times = (ctypes.c_float * 64)()
+        n = ctypes.c_int32(0)
+        _check(lib.gs_autotune(self._h, batch.handle, workspace.data_ptr(), workspace.numel(), ids.data_ptr(),
+                               sc.data_ptr(), int(reps), _stream_ptr(stream), ctypes.byref(best), cands, times, 64,
+                               ctypes.byref(n)), "gs_autotune")
+        table = [({"kernel": cands[i].kernel, "tile_docs": cands[i].tile_docs, "chunk": cands[i].chunk},
+                  float(times[i])) for i in range(min(n.value, 64))]
+        _TUNED[key] = (best, table)
+        return best, table
 
     def close(self):
         if getattr(self, "_h", None):

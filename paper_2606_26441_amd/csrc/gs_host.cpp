@@ -920,6 +920,71 @@ int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspa
     return GS_OK;
 }
 
+int32_t gs_autotune(gs_index ix, gs_batch b, void* workspace, size_t workspace_bytes_, int32_t* out_ids,
+                    void* out_scores, int32_t reps, void* hip_stream, gs_search_opts* best, gs_search_opts* cands,
+                    float* times_ms, int32_t max_candidates, int32_t* n_candidates) {
+    g_err.clear();
+    if (!ix || !b || !best) return fail(GS_EINVAL, "null argument");
+    if (reps < 1) return fail(GS_EINVAL, "reps < 1");
+    std::vector<gs_search_opts> cand;
+    const int kernels[2] = {GS_KERNEL_TILED, GS_KERNEL_SHARED};
+    std::vector<int> tiles = {8192, 16384};
+    if (ix->precision == kU8) tiles.push_back(32768);
+    for (int k : kernels)
+        for (int t : tiles)
+            for (int c : {128, 256, 512, 1024}) {
+                gs_search_opts o{};
+                o.kernel = k;
+                o.tile_docs = t;
+                o.chunk = c;
+                cand.push_back(o);
+            }
+    DeviceGuard g(ix->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GS_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GS_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+    }
+    float best_ms = 0.0f;
+    int best_i = -1;
+    int32_t rc = GS_OK;
+    for (size_t i = 0; i < cand.size() && rc == GS_OK; i++) {
+        ScoreOpts so;
+        int32_t qt = 1;
+        rc = plan_search(ix, b, workspace_bytes_, &cand[i], &so, &qt);
+        if (rc != GS_OK) break;
+        rc = enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, s, false);  // untimed
+        if (rc != GS_OK) break;
+        he = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && rc == GS_OK && he == hipSuccess; r++)
+            rc = enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, s, false);
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) rc = fail(GS_EHIP, std::string("autotune timing: ") + hipGetErrorString(he));
+        if (rc != GS_OK) break;
+        ms /= (float)reps;
+        if ((int32_t)i < max_candidates) {
+            if (cands) cands[i] = cand[i];
+            if (times_ms) times_ms[i] = ms;
+        }
+        if (best_i < 0 || ms < best_ms) {
+            best_ms = ms;
+            best_i = (int)i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != GS_OK) return rc;
+    if (n_candidates) *n_candidates = (int32_t)cand.size();
+    *best = cand[(size_t)best_i];
+    return GS_OK;
+}
+
 int32_t gs_graph_launch(gs_graph gr, void* hip_stream) {
     g_err.clear();
     if (!gr) return fail(GS_EINVAL, "graph is null");
