@@ -166,7 +166,8 @@ def run_batched(gs, torch, docs, args):
         diag = batch.diagnostics()
         got_ids, got_sc = ids.cpu().numpy(), sc.cpu().numpy()
         graph.close()
-        del ws
+        del graph, ws, ids, sc
+        torch.cuda.empty_cache()
         # small batch (16 queries): where launch overhead matters
         small = queries.subset(np.arange(16))
         sb = idx.batch(small, k[:16], k_max=1000)
@@ -221,7 +222,7 @@ def run_batched(gs, torch, docs, args):
         sb.close()
         batch.close()
         idx.close()
-        del sws, ids, sc, sids, ssc
+        del g16, sws, sids, ssc
         torch.cuda.empty_cache()
     return res
 

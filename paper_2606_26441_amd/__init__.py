@@ -338,6 +338,7 @@ class Graph:
         if getattr(self, "_h", None):
             lib.gs_graph_free(self._h)
             self._h = None
+        self._keep = None  # releases the buffers the graph was bound to
 
     def __del__(self):
         try:
