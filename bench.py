@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--batched", default="u8,bf16",
                     help="precisions for the 4,096-query uneven batch (autotuned, graph vs plain), or 'none'")
     ap.add_argument("--batched-queries", type=int, default=4096)
+    ap.add_argument("--serving", default="200,800,2000", help="Poisson arrival rates (QPS) for the serving loop, or 'none'")
+    ap.add_argument("--serving-seconds", type=float, default=8.0)
+    ap.add_argument("--serving-precision", default="u8")
     return ap.parse_args()
 
 
@@ -227,6 +230,65 @@ def run_batched(gs, torch, docs, args):
     return res
 
 
+def run_serving(gs, torch, docs, args):
+    """Poisson arrivals into the continuous-batching loop; latency = submission to results on the host."""
+    import threading
+    import workload
+
+    prec = args.serving_precision
+    idx = gs.Index.from_rows(docs, prec)
+    pool = workload.queries_lognormal(8192, seed=91)
+    ks = workload.k_mix(8192, seed=92)
+    max_batch, n_slots = 32, 4
+    srv = gs.Server(idx, max_batch=max_batch, n_slots=n_slots, k_max=1000, opts=gs.make_opts("tiled"))
+    res = {"precision": prec, "max_batch": max_batch, "n_slots": n_slots, "slot_bytes": srv.stats()["slot_bytes"],
+           "query_law": "lognormal median 25, sigma 0.8, [5, 250]; k over {10, 100, 1000}"}
+    for q in range(64):  # warm-up
+        t, w = pool.row(q)
+        srv.wait(srv.submit(t, w, int(ks[q])), int(ks[q]))
+    for rate in [float(r) for r in args.serving.split(",") if r]:
+        arrivals = workload.poisson_arrivals(rate, args.serving_seconds, seed=int(rate))
+        n = arrivals.shape[0]
+        tickets = [None] * n
+        lat = np.zeros(n)
+        done_at = np.zeros(n)
+
+        def collector():
+            for i in range(n):
+                while tickets[i] is None:
+                    time.sleep(1e-5)
+                kq = int(ks[i % 8192])
+                _, _, lat[i] = srv.wait(tickets[i], kq)
+                done_at[i] = time.perf_counter()
+
+        before = srv.stats()
+        th = threading.Thread(target=collector)
+        th.start()
+        t0 = time.perf_counter()
+        for i in range(n):
+            now = time.perf_counter() - t0
+            if arrivals[i] > now:
+                time.sleep(arrivals[i] - now)
+            t, w = pool.row(i % 8192)
+            tickets[i] = srv.submit(t, w, int(ks[i % 8192]))
+        th.join()
+        span = max(done_at.max() - t0, args.serving_seconds)
+        after = srv.stats()
+        steps = after["device_steps"] - before["device_steps"]
+        res["rate_%d" % int(rate)] = {
+            "offered_qps": rate, "requests": n, "sustained_qps": round(n / span, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_batch": round((after["completed"] - before["completed"]) / max(steps, 1), 2),
+            "max_in_flight": after["max_in_flight"]}
+        log("serving %s @%d QPS: sustained %.1f, p50 %.2f ms, p99 %.2f ms, mean batch %.1f"
+            % (prec, rate, n / span, np.percentile(lat, 50), np.percentile(lat, 99),
+               res["rate_%d" % int(rate)]["mean_batch"]))
+    srv.close()
+    idx.close()
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -380,6 +442,8 @@ def main():
         log("parity: %s" % checked)
     if not args.profile and args.batched != "none":
         out["batched"] = run_batched(gs, torch, docs, args)
+    if not args.profile and args.serving != "none":
+        out["serving"] = run_serving(gs, torch, docs, args)
     for f in forms.values():
         f.pop("_res", None)
     if forms:

@@ -46,7 +46,8 @@ enum gs_status {
     GS_ENOMEM = -2,       /* host or device allocation failed */
     GS_EHIP = -3,         /* a HIP runtime call failed */
     GS_ECAPACITY = -4,    /* workspace or output too small */
-    GS_EUNSUPPORTED = -5  /* option not available for this index */
+    GS_EUNSUPPORTED = -5, /* option not available for this index */
+    GS_ETIMEOUT = -6      /* gs_server_wait: the request has not finished in time */
 };
 
 /* Posting-weight storage (the paper stores fp32, Sec. 3.1; compressed
@@ -292,6 +293,69 @@ int32_t gs_timing_read(double* score_ms, int64_t* score_launches, double* select
  * in each direction). Asynchronous. Errors: GS_EINVAL, GS_EHIP.
  */
 int32_t gs_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+/* ------------------------------------------------------------- serving -- */
+
+/*
+ * Continuous-batching request loop over one resident index (the paper lists
+ * streaming query batching for serving as future work (3), Sec. 8).
+ * Requests queue as they arrive. A scheduler thread owns n_slots device slots,
+ * each with its own HIP stream, a reusable batch of max_batch queries, a
+ * workspace holding one score array per query and pinned result rows.
+ * Whenever a slot is free it takes up to max_batch waiting requests (oldest
+ * first) and runs their search while other slots keep running, so requests
+ * that arrive while others are on the GPU join as slots free up. Admission is
+ * by memory: with memory_budget > 0, n_slots is reduced so that all slots'
+ * workspaces (n_docs x 4 B per query plus selection scratch) fit the budget.
+ * Results are identical to a search of the same query alone (the integer and
+ * fixed-point sums do not depend on the batch).
+ */
+typedef struct gs_server_s* gs_server;
+
+typedef struct gs_server_opts {
+    int32_t max_batch;     /* most queries in one device step */
+    int32_t n_slots;       /* concurrent device steps (streams) */
+    int32_t k_max;         /* largest k a request may ask for (<= GS_MAX_K) */
+    int32_t reserved;      /* must be 0 */
+    int64_t memory_budget; /* device bytes for all slots' workspaces (0: no limit) */
+    gs_search_opts search; /* kernel options used for every step */
+} gs_server_opts;
+
+typedef struct gs_server_stats_t {
+    int32_t n_slots;
+    int32_t max_batch;
+    int64_t completed;     /* requests finished */
+    int64_t device_steps;  /* searches run */
+    double mean_batch;     /* requests per search */
+    int64_t max_in_flight; /* most requests on the device at once */
+    int64_t pending;       /* requests waiting for a slot now */
+    int64_t slot_bytes;    /* workspace bytes of one slot */
+} gs_server_stats_t;
+
+/* Allocates every slot up front (device and pinned memory) and starts the
+ * scheduler. Errors: GS_EINVAL, GS_ECAPACITY (budget below one slot),
+ * GS_ENOMEM, GS_EHIP. */
+int32_t gs_server_create(gs_index index, const gs_server_opts* opts, gs_server* out);
+
+/* Queue one query (host arrays, copied). Returns a ticket >= 0, or a negative
+ * gs_status (GS_EINVAL: bad term, weight, duplicate, nnz > GS_MAX_QUERY_NNZ,
+ * k outside [0, k_max]). Thread-safe. */
+int64_t gs_server_submit(gs_server server, const int32_t* term_ids, const float* weights, int32_t nnz,
+                         int32_t k);
+
+/* Wait for a ticket (timeout_ms < 0: no limit), then copy its k ids and scores
+ * (float, double for GS_BF16, int32 for GS_U8) to host memory and give its
+ * latency from submission to completion in ms. Each ticket can be collected
+ * once. Thread-safe. Errors: GS_EINVAL (unknown or already collected ticket),
+ * GS_ETIMEOUT, or the status of a failed search. */
+int32_t gs_server_wait(gs_server server, int64_t ticket, int32_t timeout_ms, int32_t* out_ids,
+                       void* out_scores, double* latency_ms);
+
+int32_t gs_server_stats(gs_server server, gs_server_stats_t* out);
+
+/* Stops the scheduler after the steps on the device finish; requests still
+ * waiting for a slot are dropped. Call after every gs_server_wait has returned. */
+void gs_server_destroy(gs_server server);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@ import torch  # loads the HIP runtime that the library then shares
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgpusparse.so")
 
-GS_OK, GS_EINVAL, GS_ENOMEM, GS_EHIP, GS_ECAPACITY, GS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GS_OK, GS_EINVAL, GS_ENOMEM, GS_EHIP, GS_ECAPACITY, GS_EUNSUPPORTED, GS_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 GS_FP32, GS_BF16, GS_U8 = 0, 1, 2
 GS_KEEP_FORWARD = 1
 GS_KERNEL_AUTO, GS_KERNEL_TILED, GS_KERNEL_ATOMIC, GS_KERNEL_DOCPAR, GS_KERNEL_SHARED = 0, 1, 2, 3, 4
@@ -39,12 +39,23 @@ class GsError(RuntimeError):
 
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error", -4: "capacity exceeded",
-           -5: "unsupported"}
+           -5: "unsupported", -6: "timeout"}
 
 
 class SearchOpts(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("query_tile", ctypes.c_int32), ("tile_docs", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("group", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("k_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("memory_budget", ctypes.c_int64), ("search", SearchOpts)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("completed", ctypes.c_int64),
+                ("device_steps", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("max_in_flight", ctypes.c_int64),
+                ("pending", ctypes.c_int64), ("slot_bytes", ctypes.c_int64)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -87,6 +98,16 @@ def _load() -> ctypes.CDLL:
     lib.gs_graph_free.restype = None
     lib.gs_autotune.argtypes = [vp, vp, vp, sz, vp, vp, i32, vp, P(SearchOpts), vp, vp, i32, P(i32)]
     lib.gs_autotune.restype = i32
+    lib.gs_server_create.argtypes = [vp, P(ServerOpts), P(vp)]
+    lib.gs_server_create.restype = i32
+    lib.gs_server_submit.argtypes = [vp, vp, vp, i32, i32]
+    lib.gs_server_submit.restype = i64
+    lib.gs_server_wait.argtypes = [vp, i64, i32, vp, vp, P(ctypes.c_double)]
+    lib.gs_server_wait.restype = i32
+    lib.gs_server_stats.argtypes = [vp, P(ServerStats)]
+    lib.gs_server_stats.restype = i32
+    lib.gs_server_destroy.argtypes = [vp]
+    lib.gs_server_destroy.restype = None
     lib.gs_workspace_size.argtypes = [vp, i32, P(SearchOpts), P(sz)]
     lib.gs_workspace_size.restype = i32
     lib.gs_search_batch.argtypes = [vp, vp, vp, sz, vp, vp, P(SearchOpts), vp]
@@ -339,6 +360,54 @@ class Graph:
             lib.gs_graph_free(self._h)
             self._h = None
         self._keep = None  # releases the buffers the graph was bound to
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (gs_server_*) over a resident index."""
+
+    def __init__(self, index: Index, max_batch: int = 32, n_slots: int = 4, k_max: int = 1000, memory_budget: int = 0,
+                 opts: Optional[SearchOpts] = None):
+        o = ServerOpts()
+        o.max_batch, o.n_slots, o.k_max, o.memory_budget = int(max_batch), int(n_slots), int(k_max), int(memory_budget)
+        if opts is not None:
+            o.search = opts
+        h = ctypes.c_void_p()
+        _check(lib.gs_server_create(index.handle, ctypes.byref(o), ctypes.byref(h)), "gs_server_create")
+        self._h, self._index = h, index
+        self.k_max = int(k_max)
+        self.score_dtype = {GS_FP32: np.float32, GS_BF16: np.float64, GS_U8: np.int32}[index.precision]
+
+    def submit(self, terms, weights, k: int) -> int:
+        t, w = _np(terms, np.int32), _np(weights, np.float32)
+        r = lib.gs_server_submit(self._h, t.ctypes.data, w.ctypes.data, t.shape[0], int(k))
+        if r < 0:
+            raise GsError(int(r), "gs_server_submit", lib.gs_last_error().decode())
+        return int(r)
+
+    def wait(self, ticket: int, k: int, timeout_ms: int = -1):
+        """(ids [k] int32, scores [k], latency ms) of a submitted query."""
+        ids = np.empty(max(k, 1), np.int32)
+        sc = np.empty(max(k, 1), self.score_dtype)
+        lat = ctypes.c_double(0)
+        _check(lib.gs_server_wait(self._h, int(ticket), int(timeout_ms), ids.ctypes.data, sc.ctypes.data,
+                                  ctypes.byref(lat)), "gs_server_wait")
+        return ids[:k], sc[:k], lat.value
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib.gs_server_stats(self._h, ctypes.byref(s)), "gs_server_stats")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.gs_server_destroy(self._h)
+            self._h = None
 
     def __del__(self):
         try:

@@ -21,7 +21,8 @@ using namespace gs;
 
 namespace gs {
 thread_local const char* g_failed_launch = "";
-}
+int32_t set_error(int32_t code, const std::string& msg);
+}  // namespace gs
 
 namespace {
 
@@ -81,6 +82,12 @@ inline uint8_t q8(float w) {
     const double x = std::nearbyint((double)w * 85.0);
     return x > 255.0 ? 255 : (x > 0.0 ? (uint8_t)x : 0);
 }
+
+}  // namespace
+
+int32_t gs::set_error(int32_t code, const std::string& msg) { return fail(code, msg); }
+
+namespace {
 
 // ----------------------------------------------------------- CSR checks --
 
@@ -442,6 +449,7 @@ const char* gs_status_string(int32_t s) {
         case GS_EHIP: return "HIP runtime error";
         case GS_ECAPACITY: return "capacity exceeded";
         case GS_EUNSUPPORTED: return "unsupported";
+        case GS_ETIMEOUT: return "timeout";
     }
     return "unknown status";
 }

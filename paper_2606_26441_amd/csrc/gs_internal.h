@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace gs {
 
 constexpr int kWave = 64;             // CDNA wavefront
@@ -19,6 +21,9 @@ constexpr int kRefinePasses = 6;      // enough to resolve any 64-bit composite 
 constexpr int kFirstShiftFloat = 52;  // first digit of a float key: bits 30..20
 
 enum Precision { kFP32 = 0, kBF16 = 1, kU8 = 2 };
+
+// Record the message returned by gs_last_error() on this thread; returns code.
+int32_t set_error(int32_t code, const std::string& msg);
 
 // Name of the kernel whose launch failed last on this thread (for error messages).
 extern thread_local const char* g_failed_launch;

@@ -34,9 +34,9 @@ def test_library_exports_every_declared_symbol():
 def test_status_strings_and_version_without_gpu():
     import paper_2606_26441_amd as gs
     assert "gfx950" in gs.version()
-    for code, text in gs._STATUS.items():
-        assert gs.lib.gs_status_string(code).decode() in (text, "ok", "invalid argument", "out of memory",
-                                                           "HIP runtime error", "capacity exceeded", "unsupported")
+    for code in gs._STATUS:
+        assert gs.lib.gs_status_string(code).decode() != "unknown status"
+    assert gs.lib.gs_status_string(-99).decode() == "unknown status"
 
 
 @pytest.mark.parametrize("case", ["term_range", "negative_weight", "nan_weight", "duplicate", "row_ptr"])
