@@ -762,7 +762,7 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
     so->kernel = GS_KERNEL_TILED;
     // 64 KiB of LDS accumulators: 8192 fixed-point (fp32, bf16) or 16384 int32 (uint8) documents
     so->tile_shift = ix->precision == kU8 ? 14 : 13;
-    so->chunk = 256;
+    so->chunk = 1024;  // measured fastest for both doc-tiled forms at every tile size
     so->group = 4;
     if (!o) return GS_OK;
     for (int i = 0; i < 3; i++)

@@ -153,12 +153,21 @@ struct TileShared {
 };
 
 // Chunk c of a tile's work (c is the same on every lane of the wavefront):
-// segment index, first posting and length, kept in scalar registers.
-__device__ __forceinline__ void chunk_at(const TileShared& sh, int nq, int c, int ch, int* seg, int64_t* p0, int* n) {
-    int lo = 0, hi = nq - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sh.seg_cpre[mid] <= c) lo = mid; else hi = mid - 1;
+// segment index, first posting and length, kept in scalar registers. The
+// segment comes from the chunk table when the tile has one, else from a binary
+// search over the chunk prefix.
+__device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* tab, int nq, int c, int ch, int* seg,
+                                         int64_t* p0, int* n) {
+    int lo;
+    if (tab) {
+        lo = tab[c];
+    } else {
+        lo = 0;
+        int hi = nq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sh.seg_cpre[mid] <= c) lo = mid; else hi = mid - 1;
+        }
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
     const int off = (c - sh.seg_cpre[lo]) * ch;
@@ -189,7 +198,6 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     const int tile_n = (int)min((int64_t)TILE, N - base);
 
     for (int i = tid; i < TILE * (FX ? 2 : 1); i += BS) lds[i] = 0u;
-    for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
 
     const int64_t qa = qb.q_row_ptr[q];
     const int nq = (int)(qb.q_row_ptr[q + 1] - qa);
@@ -240,7 +248,18 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // Chunks go round-robin to the wavefronts. Each wavefront keeps two chunks in
     // flight: the loads of its next chunk are issued before the LDS adds of the
     // current one (two register sets, alternating).
+    // Chunk table: during accumulation the histogram's LDS holds the segment index
+    // of every chunk (one byte each), so a wavefront finds its chunk's segment with
+    // one LDS read; tiles with more chunks than it holds fall back to a search.
     const int total = sh.seg_cpre[nq];
+    const uint8_t* tab = nullptr;
+    if (total <= kHistBins * 4) {
+        uint8_t* t8 = reinterpret_cast<uint8_t*>(hist);
+        for (int sgi = 0; sgi < nq; sgi++)
+            for (int c = sh.seg_cpre[sgi] + tid; c < sh.seg_cpre[sgi + 1]; c += BS) t8[c] = (uint8_t)sgi;
+        tab = t8;
+        __syncthreads();
+    }
     struct Chunk {
         int doc[U];
         uint32_t w[U];
@@ -253,7 +272,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         int64_t p0 = 0;
         k.seg = 0;
         k.n = 0;
-        if (valid) chunk_at(sh, nq, c, CH, &k.seg, &p0, &k.n);
+        if (valid) chunk_at(sh, tab, nq, c, CH, &k.seg, &p0, &k.n);
         const int last = max(k.n - 1, 0);
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -290,14 +309,19 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         c = ca;
     }
     __syncthreads();
+    for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
+    __syncthreads();
     flush_tile<BS, FX>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
                        FX ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins);
 }
 
 // Per-query form: grid (tiles, queries), the tiles of one query are consecutive
 // workgroups, so each query streams its own postings from HBM.
+// Both scoring kernels are held to 128 VGPRs (four wavefronts per SIMD): two
+// 512-thread workgroups per CU, which is what their LDS footprint allows.
 template <int P, int TS, int CH>
-__global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_tiled(
+    DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
                                                      int64_t ld, uint32_t* __restrict__ hist1) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ TileShared sh;
@@ -311,7 +335,8 @@ __global__ __launch_bounds__(512) void k_score_tiled(DevIndex ix, DevBatch qb, i
 // every query of a tile runs on one XCD while the tile's postings are in its L2.
 // Every workgroup leaves the loop once its XCD's counter passes the item count.
 template <int P, int TS, int CH>
-__global__ __launch_bounds__(512) void k_score_persistent(DevIndex ix, DevBatch qb, int32_t q0, int32_t qt,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_persistent(
+    DevIndex ix, DevBatch qb, int32_t q0, int32_t qt,
                                                           const int32_t* __restrict__ order,
                                                           uint32_t* __restrict__ counters, uint32_t* __restrict__ S,
                                                           int64_t ld, uint32_t* __restrict__ hist1) {

@@ -156,6 +156,9 @@ __global__ __launch_bounds__(64) void k_refine_select(DevBatch qb, int32_t q0, i
     }
 }
 
+// Append every composite >= the query's threshold to its candidate buffer.
+// Each lane reads four consecutive scores with one 16-byte load (rows are
+// 64-aligned); the wavefront appends with one ballot + popcount per column.
 __global__ __launch_bounds__(512) void k_filter(int32_t q0, int64_t N, const uint32_t* __restrict__ S, int64_t ld,
                                                 int per_block, SelState* __restrict__ state,
                                                 unsigned long long* __restrict__ cand) {
@@ -164,25 +167,27 @@ __global__ __launch_bounds__(512) void k_filter(int32_t q0, int64_t N, const uin
     if (st->resolved != 1) return;
     const unsigned long long lo = st->lo;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
-    const int64_t d0 = (int64_t)blockIdx.x * per_block, d1 = min(N, d0 + per_block);
+    const int64_t d0 = (int64_t)blockIdx.x * per_block, d1 = min(N, d0 + per_block);  // per_block % 256 == 0
     const uint32_t* Sq = S + (int64_t)ql * ld;
     unsigned long long* C = cand + (int64_t)ql * kCandCap;
-    for (int64_t wb = d0 + wave * kWave; wb < d1; wb += 512) {
-        const int64_t d = wb + lane;
-        unsigned long long c = 0;
-        bool take = false;
-        if (d < d1) {
-            c = comp_key(Sq[d], (uint32_t)d);
-            take = c >= lo;
-        }
-        const unsigned long long m = __ballot(take);
-        if (m == 0) continue;
-        int slot = 0;
-        if (lane == 0) slot = atomicAdd(&st->n_cand, __popcll(m));
-        slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
-        if (take) {
-            if (slot < kCandCap) C[slot] = c;
-            else st->overflow = 1;
+    for (int64_t wb = d0 + (int64_t)wave * kWave * 4; wb < d1; wb += 512 * 4) {
+        const int64_t d = wb + (int64_t)lane * 4;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (d < d1) v = *reinterpret_cast<const uint4*>(Sq + d);  // d + 3 < ld: rows are padded to 64
+        const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const unsigned long long c = comp_key(vs[j], (uint32_t)(d + j));
+            const bool take = d + j < d1 && c >= lo;
+            const unsigned long long m = __ballot(take);
+            if (m == 0) continue;
+            int slot = 0;
+            if (lane == 0) slot = atomicAdd(&st->n_cand, __popcll(m));
+            slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
+            if (take) {
+                if (slot < kCandCap) C[slot] = c;
+                else st->overflow = 1;
+            }
         }
     }
 }
