@@ -175,6 +175,8 @@ int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
 int32_t gs_batch_create(gs_index index, const int64_t* q_row_ptr, int32_t n_queries,
                         const int32_t* q_term_ids, const float* q_weights, int64_t q_nnz,
                         const int32_t* k, int32_t k_max, void* hip_stream, gs_batch* out);
+/* Frees a batch (also after its index was freed). A batch may only be searched
+ * while the index it was created for is alive. */
 void gs_batch_free(gs_batch batch);
 
 /*

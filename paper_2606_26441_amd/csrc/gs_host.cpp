@@ -307,7 +307,8 @@ struct gs_index_s {
 };
 
 struct gs_batch_s {
-    gs_index index = nullptr;
+    gs_index index = nullptr;          // borrowed: must outlive searches, not needed to free the batch
+    int device = 0;                    // device holding the batch's memory
     int32_t n_queries = 0, k_max = 0;  // capacity in queries (launch shapes use it)
     int64_t q_nnz = 0;                 // capacity in query terms
     int32_t n_active = 0;              // queries set by the last update
@@ -337,7 +338,7 @@ int32_t dev_upload(std::vector<void*>& allocs, size_t& bytes, const T* host, siz
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        if (dev >= 0 && hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
         else prev = -1;
     }
     ~DeviceGuard() {
@@ -607,6 +608,7 @@ int32_t gs_batch_reserve(gs_index ix, int32_t max_queries, int64_t max_nnz, int3
     gs_batch b = new (std::nothrow) gs_batch_s();
     if (!b) return fail(GS_ENOMEM, "host allocation failed");
     b->index = ix;
+    b->device = ix->device;
     b->n_queries = max_queries;
     b->k_max = k_max;
     b->q_nnz = max_nnz;
@@ -754,7 +756,7 @@ int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries
 
 void gs_batch_free(gs_batch b) {
     if (!b) return;
-    DeviceGuard g(b->index ? b->index->device : 0);
+    DeviceGuard g(b->device);
     delete b;
 }
 
@@ -1071,7 +1073,7 @@ int32_t gs_batch_diagnostics(gs_batch b, int32_t* out) {
     g_err.clear();
     if (!b || !out) return fail(GS_EINVAL, "null argument");
     if (b->n_queries == 0) return GS_OK;
-    DeviceGuard g(b->index->device);
+    DeviceGuard g(b->device);
     GS_HIP(hipMemcpy(out, b->diag, (size_t)b->n_queries * 16, hipMemcpyDeviceToHost));
     return GS_OK;
 }

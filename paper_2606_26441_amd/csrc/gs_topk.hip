@@ -439,13 +439,21 @@ __global__ __launch_bounds__(1024) void k_band_final(DevIndex ix, DevBatch qb, i
         sq_w[i] = qb.q_w[qa + i];
     }
     __syncthreads();
+    const int64_t kq = kq_of(qb, q, ix.n_docs);
+    if (st->overflow) {
+        // the band does not fit the buffer: the row is left as padding and flagged
+        for (int i = tid; i < kq; i += 1024) {
+            out_ids[(int64_t)q * qb.k_max + i] = -1;
+            out_scores[(int64_t)q * qb.k_max + i] = 0.0;
+        }
+        return;
+    }
     const int nb = min(st->band, kCandCap);
     double* bs = band_s + (int64_t)ql * kCandCap;
     int32_t* bid = band_id + (int64_t)ql * kCandCap;
     for (int i = tid; i < nb; i += 1024) bs[i] = rescore_f64(ix, bid[i], sq_t, sq_w, nq);
     __threadfence_block();
     __syncthreads();
-    const int64_t kq = kq_of(qb, q, ix.n_docs);
     rank_band(bs, bid, nb, kq, out_ids + (int64_t)q * qb.k_max, out_scores + (int64_t)q * qb.k_max);
 }
 

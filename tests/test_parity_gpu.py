@@ -209,3 +209,72 @@ def test_mid_scale_top1000(mid, precision, kernel):
     docs, qs = mid
     ids, sc, diag = _run(gs, docs, qs, 1000, precision, kernel)
     check_batch(precision, docs, qs, ids, sc, 1000, what="1M %s %s" % (precision, kernel))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "u8"])
+def test_refinement_rounds_resolve_massive_exact_ties(precision):
+    # every document holds term 0 with weight 1 and the query is {0: 1}: all 150,000 docs tie
+    # exactly, the first digit bucket overflows the candidate buffer and the answer is decided by
+    # doc id through the refinement rounds
+    gs = _gs()
+    rng = np.random.default_rng(21)
+    rows = []
+    for _ in range(150_000):
+        extra = rng.choice(np.arange(1, 24), size=int(rng.integers(0, 3)), replace=False)
+        rows.append([(0, 1.0)] + [(int(e), float(rng.integers(1, 3))) for e in sorted(extra)])
+    docs = csr(rows, 24)
+    qs = csr([[(0, 1.0)], [(0, 1.0), (5, 1.0)], [(0, 0.5)]], 24)
+    k = [1000, 4000, 7]
+    ids, sc, diag = _run(gs, docs, qs, k, precision, "tiled", k_max=4096)
+    assert diag[0, 1] > 0, "the all-tied query needed no refinement round"
+    check_batch(precision, docs, qs, ids, sc, k, what="refine " + precision)
+
+
+def test_bf16_band_beyond_capacity_is_flagged_not_wrong():
+    # with the same exact ties the bf16 rescoring band holds every document: beyond the
+    # candidate buffer, so the row must be flagged as overflowed
+    gs = _gs()
+    rows = [[(0, 1.0)] for _ in range(60_000)]
+    docs = csr(rows, 4)
+    qs = csr([[(0, 1.0)]], 4)
+    idx = gs.Index.from_rows(docs, "bf16")
+    b = idx.batch(qs, [100], k_max=100)
+    idx.search(b, idx.workspace(1))
+    import torch
+    torch.cuda.synchronize()
+    assert b.diagnostics()[0, 3] == 1
+
+
+@pytest.fixture(scope="module")
+def full():
+    w = workload.WORKLOADS["full-8.8m"]
+    return workload.make_collection(w), workload.make_queries(w)
+
+
+@pytest.mark.parametrize("precision,kernel", [("fp32", "tiled"), ("u8", "shared"), ("bf16", "shared")])
+def test_full_scale_sampled(full, precision, kernel):
+    # the benchmark's configuration: 8.8M docs, all 500 queries in one launch, top-1000; the oracle
+    # checks a sample of queries completely and every returned score of every query one by one
+    gs = _gs()
+    import torch
+    docs, qs = full
+    idx = gs.Index.from_rows(docs, precision)
+    opts = gs.make_opts(kernel)
+    b = idx.batch(qs, 1000)
+    ids, sc = idx.search(b, idx.workspace(qs.n_rows, opts), opts)
+    torch.cuda.synchronize()
+    assert b.diagnostics()[:, 3].max() == 0
+    ids, sc = ids.cpu().numpy(), sc.cpu().numpy()
+    sample = qs.subset(np.arange(6))
+    check_batch(precision, docs, sample, ids[:6], sc[:6], 1000, n_threads=0, what="8.8M " + precision)
+    for q in range(0, qs.n_rows, 25):  # every 25th query: returned scores are the exact scores of those docs
+        t, w = qs.row(q)
+        f, i = oracle.pair_scores(docs, t, w, ids[q])
+        if precision == "u8":
+            assert np.array_equal(sc[q].astype(np.int64), i)
+        elif precision == "bf16":
+            assert np.array_equal(sc[q], f)
+        else:
+            assert np.max(np.abs(sc[q] - f) / f) < 1e-5
+        assert np.all(np.diff(sc[q]) <= 0) and np.unique(ids[q]).shape[0] == 1000
+    idx.close()
