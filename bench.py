@@ -330,6 +330,10 @@ def main():
     main_res = time_form(gs, torch, docs, queries, args.k, args.precision, opts, args.steps, args.warmup,
                          keep_forward=(args.kernel == "docpar"))
     p_q, score_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision])
+    if args.kernel == "docpar":
+        # document-parallel: every forward row (term id + fp32 weight) per query, plus one score write
+        score_bytes = nq * (docs.nnz * 8 + n_docs * 4)
+        step_bytes = score_bytes + nq * n_docs * 4
     ms_per_step = main_res["total_ms"] / args.steps
     qps = nq * args.steps / (main_res["total_ms"] / 1e3)
     t = main_res["timing"]
@@ -359,7 +363,8 @@ def main():
                    "precision": args.precision, "kernel": args.kernel, "tile_docs": args.tile_docs or (16384 if args.precision == "u8" else 8192),
                    "chunk": args.chunk or 256, "query_nnz_mean": round(queries.nnz / max(nq, 1), 2),
                    "postings_per_query_mean": int(p_q.mean())},
-        "roofline": {"bound": "hbm", "kernel": "k_score_tiled" if args.kernel == "tiled" else "score_" + args.kernel,
+        "roofline": {"bound": "hbm", "kernel": {"tiled": "k_score_tiled", "shared": "k_score_persistent",
+                                                "atomic": "k_score_atomic", "docpar": "k_score_docpar"}[args.kernel],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_source": traffic_src,
@@ -386,7 +391,8 @@ def main():
             name = prec if kern == "tiled" else prec + ":" + kern
             log("form %s ..." % name)
             fsteps = max(3, args.steps // 2)
-            r = time_form(gs, torch, docs, queries, args.k, prec, gs.make_opts(kern), fsteps, 1)
+            r = time_form(gs, torch, docs, queries, args.k, prec, gs.make_opts(kern), fsteps, 1,
+                          keep_forward=(kern == "docpar"))
             ms = r["total_ms"] / fsteps
             t = r["timing"]
             forms[name] = {"qps": round(nq / (ms / 1e3), 2), "ms_per_step": round(ms, 3),

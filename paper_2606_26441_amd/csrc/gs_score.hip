@@ -453,6 +453,11 @@ __global__ __launch_bounds__(256) void k_score_atomic(DevIndex ix, DevBatch qb, 
 
 // ------------------------------------------------------------ docpar --
 
+// 1024 threads per (query, block of docs): the query's weights sit in a dense
+// LDS table; a wavefront scores 4 documents at a time, 16 lanes per document,
+// each lane walking its document's forward row with stride 16 and four loads
+// of (term, weight) in flight, then a 16-lane reduction. Rows are contiguous,
+// so the 4 x 16 lanes read 4 short coalesced runs per step.
 template <int P>
 __global__ __launch_bounds__(1024) void k_score_docpar(DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
                                                        int64_t ld, int docs_per_block) {
@@ -468,16 +473,36 @@ __global__ __launch_bounds__(1024) void k_score_docpar(DevIndex ix, DevBatch qb,
         table[qb.q_term[qa + t]] = WF<P>::bits(v);
     }
     __syncthreads();
+    if (qb.k[q] == 0) return;
     const Acc* tab = reinterpret_cast<const Acc*>(table);
     const int64_t d0 = (int64_t)blockIdx.x * docs_per_block;
     const int64_t d1 = min(ix.n_docs, d0 + docs_per_block);
     uint32_t* Sq = S + (int64_t)ql * ld;
-    for (int64_t d = d0 + wave; d < d1; d += 16) {
-        const int64_t a = ix.fwd_row_ptr[d], b = ix.fwd_row_ptr[d + 1];
+    const int grp = lane >> 4, sub = lane & 15;
+    for (int64_t dg = d0 + (int64_t)wave * 4; dg < d1; dg += 16 * 4) {
+        const int64_t d = dg + grp;
+        int64_t a = 0, b = 0;
+        if (d < d1) {
+            a = ix.fwd_row_ptr[d];
+            b = ix.fwd_row_ptr[d + 1];
+        }
         Acc s = 0;
-        for (int64_t j = a + lane; j < b; j += kWave) s += tab[ix.fwd_term[j]] * WF<P>::from_fp32(ix.fwd_w[j]);
-        s = wave_sum(s);
-        if (lane == 0) Sq[d] = WF<P>::bits(s);
+        for (int64_t e = a + sub; e < b; e += 64) {
+            int t[4];
+            float w[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int64_t eu = e + 16 * u;
+                t[u] = eu < b ? ix.fwd_term[eu] : 0;
+                w[u] = eu < b ? ix.fwd_w[eu] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (e + 16 * u < b) s += tab[t[u]] * WF<P>::from_fp32(w[u]);
+        }
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+        if (sub == 0 && d < d1) Sq[d] = WF<P>::bits(s);
     }
 }
 
