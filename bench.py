@@ -62,10 +62,14 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(df, queries, n_docs, wbytes):
-    """Per-query postings of the query's terms (doc id + weight) and one score-array write / read."""
+def algorithmic_bytes(df, queries, n_docs, wbytes, idbytes):
+    """Per-query postings of the query's terms (doc id + weight) and one score-array write / read.
+
+    The doc-tiled kernels read a 16-bit in-tile doc offset (idbytes 2); the global-atomic
+    kernel reads the 32-bit doc id (idbytes 4).
+    """
     p_q = np.array([int(df[queries.row(i)[0]].sum()) for i in range(queries.n_rows)], dtype=np.int64)
-    score_kernel = int(p_q.sum()) * (4 + wbytes) + queries.n_rows * n_docs * 4
+    score_kernel = int(p_q.sum()) * (idbytes + wbytes) + queries.n_rows * n_docs * 4
     step = score_kernel + queries.n_rows * n_docs * 4
     return p_q, score_kernel, step
 
@@ -87,6 +91,55 @@ def profiled_traffic(kernel, precision, workload_name):
         if h.hexdigest() == meta["source_sha256"]:
             return int(meta["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
+
+
+def score_error(oracle, docs, queries, s, k, rid, results):
+    """Error of each precision against the exact fp64 scores, on the first s queries.
+
+    fp32: relative error of the returned scores. u8: recall of the fp64 top-k and the
+    relative error of the dequantised impact score S8/85^2. bf16: the returned scores are
+    fp64-rescored (exact); the error before rescoring is that of bf16-rounded posting
+    weights, evaluated exactly on the returned docs.
+    """
+    import workload
+
+    out = {}
+    for prec, res in results:
+        if prec in out:
+            continue
+        rel, recall = [], []
+        if prec == "bf16":
+            u = docs.weights.view(np.uint32).astype(np.uint64)
+            u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+            rounded = workload.SparseRows(docs.row_ptr, docs.terms, u.view(np.float32), docs.vocab)
+        for q in range(s):
+            t_, w_ = queries.row(q)
+            kq = min(int(k), docs.n_rows)
+            ids = np.asarray(res["ids"][q][:kq])
+            exact, _ = oracle.pair_scores(docs, t_, w_, ids)
+            nz = exact > 0
+            if prec == "fp32":
+                got = np.asarray(res["scores"][q][:kq], dtype=np.float64)
+            elif prec == "u8":
+                got = np.asarray(res["scores"][q][:kq], dtype=np.float64) / 7225.0
+                recall.append(len(set(ids.tolist()) & set(np.asarray(rid[q][:kq]).tolist())) / kq)
+            else:
+                got, _ = oracle.pair_scores(rounded, t_, w_, ids)
+            rel.append(np.abs(got[nz] - exact[nz]) / exact[nz])
+        rel = np.concatenate(rel) if rel else np.zeros(0)
+        e = {"queries": s, "results": int(rel.size),
+             "rel_err_max": float("%.3g" % rel.max()) if rel.size else 0.0,
+             "rel_err_mean": float("%.3g" % rel.mean()) if rel.size else 0.0}
+        if prec == "u8":
+            e["what"] = "dequantised int32 score S8/85^2 vs exact fp64 score"
+            e["recall_at_k_mean"] = round(float(np.mean(recall)), 4)
+            e["recall_at_k_min"] = round(float(np.min(recall)), 4)
+        elif prec == "bf16":
+            e["what"] = "before fp64 rescoring (bf16-rounded posting weights); returned scores are exact"
+        else:
+            e["what"] = "returned fp32 score vs exact fp64 score"
+        out[prec] = e
+    return out
 
 
 def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_forward=False):
@@ -329,7 +382,8 @@ def main():
     log("main form: %s / %s, %d warmup + %d timed steps" % (args.precision, args.kernel, args.warmup, args.steps))
     main_res = time_form(gs, torch, docs, queries, args.k, args.precision, opts, args.steps, args.warmup,
                          keep_forward=(args.kernel == "docpar"))
-    p_q, score_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision])
+    p_q, score_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision],
+                                                   2 if args.kernel in ("tiled", "shared") else 4)
     if args.kernel == "docpar":
         # document-parallel: every forward row (term id + fp32 weight) per query, plus one score write
         score_bytes = nq * (docs.nnz * 8 + n_docs * 4)
@@ -361,7 +415,7 @@ def main():
         "data": "synthetic (seeded Zipf(1.1)/Poisson/lognormal stand-in for MS MARCO + SPLADE)",
         "config": {"workload": w.name, "n_docs": n_docs, "postings": docs.nnz, "batch": nq, "k": args.k,
                    "precision": args.precision, "kernel": args.kernel, "tile_docs": args.tile_docs or (16384 if args.precision == "u8" else 8192),
-                   "chunk": args.chunk or 256, "query_nnz_mean": round(queries.nnz / max(nq, 1), 2),
+                   "chunk": args.chunk or 1024, "query_nnz_mean": round(queries.nnz / max(nq, 1), 2),
                    "postings_per_query_mean": int(p_q.mean())},
         "roofline": {"bound": "hbm", "kernel": {"tiled": "k_score_tiled", "shared": "k_score_persistent",
                                                 "atomic": "k_score_atomic", "docpar": "k_score_docpar"}[args.kernel],
@@ -446,6 +500,10 @@ def main():
             checked["error"] = str(e)[:200]
         out["parity_sample"] = checked
         log("parity: %s" % checked)
+        out["score_error"] = score_error(oracle, docs, queries, s, args.k, rid,
+                                         [(args.precision, main_res)] + [(n.split(":")[0], f["_res"])
+                                                                         for n, f in forms.items()])
+        log("score error: %s" % out["score_error"])
     if not args.profile and args.batched != "none":
         out["batched"] = run_batched(gs, torch, docs, args)
     if not args.profile and args.serving != "none":

@@ -53,9 +53,11 @@ enum gs_status {
 /* Posting-weight storage (the paper stores fp32, Sec. 3.1; compressed
  * posting scores are its future work (2), Sec. 8). */
 enum gs_precision {
-    GS_FP32 = 0, /* fp32 weights, fp32 accumulation; scores are float */
-    GS_BF16 = 1, /* bf16 weights (round to nearest even), fp32 accumulation, then
-                    fp64 rescoring of every candidate within the bf16 error band of
+    GS_FP32 = 0, /* fp32 weights; products summed in 64-bit fixed point (per-query
+                    scale), scores are float */
+    GS_BF16 = 1, /* bf16 weights (round to nearest even); approximate scores from
+                    32-bit fixed-point sums (per-query scale bounding every doc's
+                    sum below 2^32 units), then fp64 rescoring of every candidate within the bf16 error band of
                     the k-th score from the fp32 forward rows; scores are double and
                     equal the fp64 sum over shared terms in ascending term order */
     GS_U8 = 2    /* uint8 impacts q8(w) = round(w*255/3) (ties to even, saturated
@@ -90,7 +92,8 @@ typedef struct gs_search_opts {
     int32_t query_tile;  /* most queries whose score arrays are live at once
                             (0 = as many as the workspace holds) */
     int32_t tile_docs;   /* doc tile of the TILED/SHARED kernels: 0 (default),
-                            8192, 16384 or 32768 */
+                            8192, 16384 or 32768 (32768: not for GS_FP32,
+                            GS_EUNSUPPORTED) */
     int32_t chunk;       /* postings per work item (TILED/ATOMIC): 0 (default),
                             64, 128, 256, 512 or 1024 */
     int32_t group;       /* queries per workgroup (SHARED): 0 (default) or 1..8 */
@@ -255,7 +258,7 @@ void gs_graph_free(gs_graph graph);
 /*
  * Autotuner: runs this batch with every candidate option set - scoring kernel
  * (GS_KERNEL_TILED, GS_KERNEL_SHARED) x tile_docs (8192, 16384; plus 32768 for
- * GS_U8) x chunk (128, 256, 512, 1024) - one untimed run then `reps` timed runs
+ * GS_BF16 and GS_U8) x chunk (128, 256, 512, 1024) - one untimed run then `reps` timed runs
  * each (HIP events on hip_stream), and writes the fastest option set to *best.
  * Optional host outputs: cands[max_candidates] (the option sets tried, in
  * order), times_ms[max_candidates] (mean search time of each), n_candidates.

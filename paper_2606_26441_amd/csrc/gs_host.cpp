@@ -541,6 +541,26 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     d.term_len = term_len;
     d.post_doc = post_doc;
     d.tile_off = tile_off;
+    {
+        uint16_t* lo = nullptr;
+        std::vector<uint16_t> low;
+        try {
+            low.resize(L.post_doc.size());
+        } catch (const std::bad_alloc&) {
+            return done(set_error(GS_ENOMEM, "host memory for the 16-bit doc offsets"));
+        }
+        const int64_t n = (int64_t)low.size();
+        const int T = std::max<int64_t>(1, std::min<int64_t>(n_workers(), n / (1 << 20) + 1));
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; t++)
+            th.emplace_back([&, t] {
+                for (int64_t i = n * t / T; i < n * (t + 1) / T; i++)
+                    low[(size_t)i] = (uint16_t)((uint32_t)L.post_doc[(size_t)i] & 0xFFFFu);
+            });
+        for (auto& x : th) x.join();
+        if ((rc = dev_upload(ix->allocs, ix->bytes, low.data(), low.size(), &lo, s))) return done(rc);
+        d.post_lo = lo;
+    }
     if (precision == kFP32) {
         float* p = nullptr;
         if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_f32.data(), L.w_f32.size(), &p, s))) return done(rc);
@@ -683,13 +703,15 @@ int32_t gs_batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries,
     std::vector<int64_t> qwork((size_t)cap, 0);
     for (int32_t q = 0; q < cap; q++) {
         uint64_t maxs = 0;
-        double maxprod = 0.0;
+        double maxprod = 0.0, sumprod = 0.0;
         const int64_t m = rp[(size_t)q + 1] - rp[(size_t)q];
         for (int64_t j = rp[(size_t)q]; j < rp[(size_t)q + 1]; j++) {
             qwork[(size_t)q] += ix->term_len[(size_t)r.term[j]];
             w8[(size_t)j] = q8(r.w[j]);
             maxs += (uint64_t)w8[(size_t)j] * 255u;
-            maxprod = std::max(maxprod, (double)r.w[j] * (double)ix->term_max[(size_t)r.term[j]]);
+            const double pm = (double)r.w[j] * (double)ix->term_max[(size_t)r.term[j]];
+            maxprod = std::max(maxprod, pm);
+            sumprod += pm;  // bound on any doc's score: the largest stored weight of every query term
         }
         if (ix->precision == kU8) {
             int hb = 0;
@@ -698,11 +720,21 @@ int32_t gs_batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries,
         } else {
             fshift[(size_t)q] = kFirstShiftFloat;
         }
-        // fixed point: units of 2^-F with every product of this query below 2^51 units
-        // (so a sum of at most 256 products stays below 2^59)
-        int ex = 0;
-        if (maxprod > 0.0) (void)std::frexp(maxprod * (1.0 + 1e-9), &ex);  // maxprod < 2^ex
-        const int F = std::min(1000, std::max(-1000, 51 - ex));
+        // fixed point in units of 2^-F. fp32 (64-bit sums): every product of this query below
+        // 2^51 units, so a sum of at most 256 products stays below 2^59. bf16 (32-bit sums):
+        // every doc's sum below 2^32 units; it is at most sumprod * 2^F plus one unit of
+        // rounding per product, and F is the largest with sumprod * 2^F + m + 2 < 2^32.
+        int ex = 0, F = 0;
+        if (ix->precision == kBF16) {
+            if (sumprod > 0.0) {
+                (void)std::frexp((4294967296.0 - (double)m - 3.0) / (sumprod * (1.0 + 1e-9)), &ex);
+                F = ex - 1;  // 2^F <= (2^32 - m - 3) / sumprod
+            }
+        } else {
+            if (maxprod > 0.0) (void)std::frexp(maxprod * (1.0 + 1e-9), &ex);  // maxprod < 2^ex
+            F = 51 - ex;
+        }
+        F = std::min(1000, std::max(-1000, F));
         qscale[(size_t)q] = std::ldexp(1.0, -F);
         // each product is within half a unit (or, raised from 0 to 1, within one unit) of exact
         qerr[(size_t)q] = (double)(m + 1) * std::ldexp(1.0, -F) * (1.0 + 1e-6);
@@ -763,7 +795,7 @@ void gs_batch_free(gs_batch b) {
 static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so) {
     so->kernel = GS_KERNEL_TILED;
     // 64 KiB of LDS accumulators: 8192 fixed-point (fp32, bf16) or 16384 int32 (uint8) documents
-    so->tile_shift = ix->precision == kU8 ? 14 : 13;
+    so->tile_shift = ix->precision == kFP32 ? 13 : 14;
     so->chunk = 1024;  // measured fastest for both doc-tiled forms at every tile size
     so->group = 4;
     if (!o) return GS_OK;
@@ -781,8 +813,8 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
         case 32768: so->tile_shift = 15; break;
         default: return fail(GS_EINVAL, "tile_docs must be 0, 8192, 16384 or 32768");
     }
-    if (so->tile_shift == 15 && ix->precision != kU8)
-        return fail(GS_EUNSUPPORTED, "tile_docs 32768 is available for GS_U8 only (LDS capacity)");
+    if (so->tile_shift == 15 && ix->precision == kFP32)
+        return fail(GS_EUNSUPPORTED, "tile_docs 32768 is not available for GS_FP32 (LDS capacity)");
     switch (o->chunk) {
         case 0: break;
         case 64: case 128: case 256: case 512: case 1024: so->chunk = o->chunk; break;
@@ -939,7 +971,7 @@ int32_t gs_autotune(gs_index ix, gs_batch b, void* workspace, size_t workspace_b
     std::vector<gs_search_opts> cand;
     const int kernels[2] = {GS_KERNEL_TILED, GS_KERNEL_SHARED};
     std::vector<int> tiles = {8192, 16384};
-    if (ix->precision == kU8) tiles.push_back(32768);
+    if (ix->precision != kFP32) tiles.push_back(32768);
     for (int k : kernels)
         for (int t : tiles)
             for (int c : {128, 256, 512, 1024}) {

@@ -45,6 +45,10 @@ struct DevIndex {
     const int64_t* term_off;   // [V+1] start of each padded list
     const int32_t* term_len;   // [V]   real postings per term
     const int32_t* post_doc;   // [padded_nnz], -1 in padding
+    // [padded_nnz] doc id modulo 65536. A doc tile of at most 32768 docs, aligned to its
+    // size, lies inside one 65536-aligned range, so the doc-tiled kernels read 2 bytes per
+    // posting for the id and recover the offset in the tile from the tile's base.
+    const uint16_t* post_lo;
     const void* post_w;        // [padded_nnz] float | bf16 bits (uint16) | uint8
     const int32_t* tile_off;   // [V][n_grains+1] posting offset (relative to the list start)
     int64_t n_grains;          // ceil(n_docs / 8192)

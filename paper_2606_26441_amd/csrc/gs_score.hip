@@ -102,20 +102,28 @@ __device__ __forceinline__ uint32_t stored_bits(const void* p, int64_t i, std::i
 
 // Write a finished LDS tile to the score array (fp32 bits or int32) and add its
 // first-digit histogram (composite key (score bits, ~doc id), digit at fs).
-template <int BS, bool FX>
+// Accumulator forms: kAccInt (int32 sums, written as they are), kAccFx32 and
+// kAccFx64 (unsigned fixed point in units of `scale`, written as fp32 bits).
+enum AccForm { kAccInt = 0, kAccFx32 = 1, kAccFx64 = 2 };
+
+template <int BS, int AF>
 __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, int tile_n, int64_t base, uint32_t* Sq,
                                            int fs, double scale, uint32_t* hist_out) {
     const int tid = threadIdx.x;
     const int n4 = tile_n >> 2;
     for (int i = tid; i < n4; i += BS) {
         uint32_t v[4];
-        if constexpr (FX) {
+        if constexpr (AF == kAccFx64) {
             const unsigned long long* acc = (const unsigned long long*)acc_v;
 #pragma unroll
             for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)acc[4 * i + j] * scale));
         } else {
             const uint4 u = reinterpret_cast<const uint4*>(acc_v)[i];
             v[0] = u.x; v[1] = u.y; v[2] = u.z; v[3] = u.w;
+            if constexpr (AF == kAccFx32) {
+#pragma unroll
+                for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)v[j] * scale));
+            }
         }
         reinterpret_cast<uint4*>(Sq)[i] = make_uint4(v[0], v[1], v[2], v[3]);
         const uint32_t d0 = (uint32_t)(base + 4 * i);
@@ -124,7 +132,8 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
     }
     for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
         uint32_t v;
-        if constexpr (FX) v = __float_as_uint((float)((double)((const unsigned long long*)acc_v)[i] * scale));
+        if constexpr (AF == kAccFx64) v = __float_as_uint((float)((double)((const unsigned long long*)acc_v)[i] * scale));
+        else if constexpr (AF == kAccFx32) v = __float_as_uint((float)((double)((const uint32_t*)acc_v)[i] * scale));
         else v = ((const uint32_t*)acc_v)[i];
         Sq[i] = v;
         atomicAdd(&hist[(comp_key(v, (uint32_t)(base + i)) >> fs) & (kHistBins - 1)], 1u);
@@ -137,12 +146,21 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
 // ------------------------------------------------------------- tiled --
 //
 // One workgroup per (query, doc tile of 2^TS docs). LDS holds the tile's
-// accumulators: unsigned 64-bit fixed point for fp32/bf16 weights (LDS integer
-// atomics run far faster than LDS float atomics on this GPU, and integer sums do
-// not depend on the order of the updates), int32 for uint8 impacts. Work inside
+// accumulators: unsigned fixed point for fp32 (64-bit) and bf16 (32-bit) weights
+// (LDS integer atomics run far faster than LDS float atomics on this GPU, and
+// integer sums do not depend on the order of the updates), int32 for uint8
+// impacts. Work inside
 // the workgroup: the query's posting segments for this tile are cut into chunks
 // of CH postings; wavefronts take chunks round-robin, each lane loads CH/64
 // postings (coalesced across the wavefront) before issuing its LDS adds.
+
+// fp32 weights: 64-bit fixed point (exact enough for the 1e-5 score rule at any
+// score). bf16 weights: 32-bit fixed point, whose scores only choose the
+// candidates that are rescored in fp64. uint8 impacts: int32.
+template <int P>
+constexpr int acc_form() {
+    return P == kFP32 ? kAccFx64 : (P == kBF16 ? kAccFx32 : kAccInt);
+}
 
 struct TileShared {
     int64_t seg_beg[kMaxQueryNnz];
@@ -186,18 +204,22 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
                                            uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
                                            uint32_t* lds, TileShared& sh) {
     constexpr int BS = 512, NW = BS / kWave, TILE = 1 << TS, U = CH / kWave, GPT = TS - kGrainShift;
-    constexpr bool FX = P != kU8;
-    unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(lds);  // [TILE] (FX)
-    uint32_t* acc32 = lds;                                                   // [TILE] (uint8)
-    uint32_t* hist = lds + TILE * (FX ? 2 : 1);                               // [kHistBins]
+    constexpr bool FX = P != kU8;                  // fixed-point products (fp32, bf16)
+    constexpr int AF = acc_form<P>();
+    constexpr int AW = AF == kAccFx64 ? 2 : 1;     // accumulator words per doc
+    unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(lds);  // [TILE] (fp32)
+    uint32_t* acc32 = lds;                                                   // [TILE] (bf16, uint8)
+    uint32_t* hist = lds + TILE * AW;                                        // [kHistBins]
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const int q = q0 + ql;
     const int64_t N = ix.n_docs;
     const int64_t base = tile << TS;
     const int tile_n = (int)min((int64_t)TILE, N - base);
+    static_assert(TS <= 16, "a doc tile must lie inside one 65536-doc range");
+    const int lbase = (int)(base & 0xFFFF);  // the tile's offset inside its 65536-doc range
 
-    for (int i = tid; i < TILE * (FX ? 2 : 1); i += BS) lds[i] = 0u;
+    for (int i = tid; i < TILE * AW; i += BS) lds[i] = 0u;
 
     const int64_t qa = qb.q_row_ptr[q];
     const int nq = (int)(qb.q_row_ptr[q + 1] - qa);
@@ -277,22 +299,28 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int64_t p = p0 + min(lane + u * kWave, last);
-            k.doc[u] = ix.post_doc[p];
+            k.doc[u] = ix.post_lo[p];
             if constexpr (P == kU8) k.w[u] = ((const uint8_t*)ix.post_w)[p];
             else k.w[u] = stored_bits(ix.post_w, p, std::integral_constant<int, P>());
         }
     };
     auto apply = [&](const Chunk& k) {
-        if constexpr (FX) {
+        if constexpr (AF == kAccFx64) {
             const double qd = sh.seg_qd[k.seg];
 #pragma unroll
             for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc64[k.doc[u] - base], fx_product(qd, k.w[u]));
+                if (lane + u * kWave < k.n) atomicAdd(&acc64[k.doc[u] - lbase], fx_product(qd, k.w[u]));
+        } else if constexpr (AF == kAccFx32) {
+            // the query's scale keeps every doc's sum below 2^32 units
+            const double qd = sh.seg_qd[k.seg];
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - lbase], (uint32_t)fx_product(qd, k.w[u]));
         } else {
             const uint32_t q8v = sh.seg_q8[k.seg];
 #pragma unroll
             for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - base], q8v * k.w[u]);
+                if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - lbase], q8v * k.w[u]);
         }
     };
     Chunk A, B;
@@ -311,7 +339,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     __syncthreads();
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
     __syncthreads();
-    flush_tile<BS, FX>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
+    flush_tile<BS, AF>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
                        FX ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins);
 }
 
@@ -556,7 +584,7 @@ template <int P, int TS, int CH>
 hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, bool persistent,
                             const Workspace& ws, int64_t ld, hipStream_t s) {
     const int64_t n_tiles = (ix.n_docs + (1 << TS) - 1) >> TS;
-    const size_t lds = (size_t)((1 << TS) * (P == kU8 ? 1 : 2) + kHistBins) * 4;
+    const size_t lds = (size_t)((1 << TS) * (acc_form<P>() == kAccFx64 ? 2 : 1) + kHistBins) * 4;
     if (lds > 150 * 1024) return hipErrorInvalidValue;
     if (lds > 65536) {
         static const hipError_t attr = [&] {
@@ -639,8 +667,9 @@ hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0
             case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
             case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
             case 15:
-                if constexpr (P == kU8) return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
-                return hipErrorInvalidValue;  // 32768 fixed-point accumulators exceed one CU's LDS
+                if constexpr (acc_form<P>() != kAccFx64)
+                    return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
+                return hipErrorInvalidValue;  // 32768 64-bit accumulators exceed one CU's LDS
         }
         return hipErrorInvalidValue;
     });

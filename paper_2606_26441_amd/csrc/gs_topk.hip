@@ -192,31 +192,162 @@ __global__ __launch_bounds__(512) void k_filter(int32_t q0, int64_t N, const uin
     }
 }
 
-// fp64 rescoring of one document (forward row sorted by term) against the
-// query held in LDS (terms ascending): ascending-term sum of exact products.
-__device__ double rescore_f64(const DevIndex& ix, int64_t doc, const int32_t* qt, const float* qw, int nq) {
-    const int64_t a = ix.fwd_row_ptr[doc], b = ix.fwd_row_ptr[doc + 1];
-    double s = 0.0;
-    int j = 0;
-    for (int64_t i = a; i < b && j < nq; i++) {
-        const int t = ix.fwd_term[i];
-        while (j < nq && qt[j] < t) j++;
-        if (j < nq && qt[j] == t) s += (double)qw[j] * (double)ix.fwd_w[i];
+// fp64 rescoring of the docs bid[0..nb) against the query held in LDS (terms
+// ascending), by the whole workgroup: a wavefront takes 4 docs, 16 lanes each.
+// Lane `sub` walks entries sub, sub+16, ... of the doc's forward row (sorted by
+// term) and merges them with the query terms; each step's nonzero products are
+// then added in row order (ascending term), one shuffle at a time, so the sum
+// is the same sequence of fp64 additions as a serial walk of the row.
+__device__ void rescore_band(const DevIndex& ix, const int32_t* bid, double* bs, int nb, const int32_t* qt,
+                             const float* qw, int nq) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int grp = lane >> 4, sub = lane & 15;
+    for (int base = wave * 4; base < nb; base += nw * 4) {
+        const int i = base + grp;
+        int64_t a = 0;
+        int len = 0;
+        if (i < nb) {
+            const int64_t doc = bid[i];
+            a = ix.fwd_row_ptr[doc];
+            len = (int)(ix.fwd_row_ptr[doc + 1] - a);
+        }
+        int maxlen = len;
+        maxlen = max(maxlen, __shfl_xor(maxlen, 16, kWave));
+        maxlen = max(maxlen, __shfl_xor(maxlen, 32, kWave));
+        double s = 0.0;
+        int j = 0;
+        for (int off = 0; off < maxlen; off += 16) {
+            const int e = off + sub;
+            double pr = 0.0;
+            if (e < len) {
+                const int t = ix.fwd_term[a + e];
+                while (j < nq && qt[j] < t) j++;
+                if (j < nq && qt[j] == t) pr = (double)qw[j] * (double)ix.fwd_w[a + e];
+            }
+            uint32_t mm = (uint32_t)(__ballot(pr != 0.0) >> (grp * 16)) & 0xFFFFu;
+            while (__any(mm != 0u)) {
+                const int src = grp * 16 + (mm ? __ffs(mm) - 1 : 0);
+                const double v = __shfl(pr, src, kWave);
+                if (mm) {
+                    s += v;
+                    mm &= mm - 1u;
+                }
+            }
+        }
+        if (sub == 0 && i < nb) bs[i] = s;
     }
-    return s;
 }
 
-// Rank band members by (fp64 score desc, id asc); write the first kq.
-__device__ void rank_band(const double* bs, const int32_t* bid, int nb, int64_t kq, int32_t* ids, double* sc) {
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        const double si = bs[i];
-        const int32_t di = bid[i];
-        int r = 0;
-        for (int j = 0; j < nb; j++) {
-            const double sj = bs[j];
-            r += (sj > si) || (sj == si && bid[j] < di);
+// One wavefront walks a 256-bin histogram from the top bin down for the bin
+// holding the need-th largest element; writes it and the count above it.
+__device__ void walk256(const uint32_t* hist, uint32_t need, int* d_out, uint32_t* above_out) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t s = 0;
+    for (int j = 0; j < 4; j++) s += hist[255 - lane * 4 - j];
+    uint32_t incl = s;
+    for (int dd = 1; dd < kWave; dd <<= 1) {
+        const uint32_t v = __shfl_up(incl, dd, kWave);
+        if (lane >= dd) incl += v;
+    }
+    const uint32_t excl = incl - s;
+    const unsigned long long m = __ballot(excl < need && need <= incl);
+    const int owner = m ? __ffsll((long long)m) - 1 : kWave - 1;
+    if (lane == owner) {
+        uint32_t run = excl;
+        int dsel = 255 - lane * 4 - 3;
+        uint32_t ab = run;
+        for (int j = 0; j < 4; j++) {
+            const uint32_t c = hist[255 - lane * 4 - j];
+            if (run + c >= need) {
+                dsel = 255 - lane * 4 - j;
+                ab = run;
+                break;
+            }
+            run += c;
         }
-        if (r < kq) { ids[r] = di; sc[r] = si; }
+        *d_out = dsel;
+        *above_out = ab;
+    }
+}
+
+// The first kq band members by (fp64 score desc, doc id asc), written to ids /
+// sc. Keys (score bits, ~doc id) are distinct and ordered like that pair (scores
+// are >= 0, so their bits are monotone): a radix select with 8-bit digits (8 of
+// the score, then 4 of ~id) finds the kq-th largest key, the kq keys at or above
+// it are gathered into LDS, and each is placed by its rank among them.
+// LDS used by band_topk: hist[256], wsc[kMaxK], wid[kMaxK] and three scalars
+// (the caller may hand in arrays it no longer needs).
+struct BandLds {
+    uint32_t* hist;
+    unsigned long long* wsc;
+    int32_t* wid;
+    int* d;
+    uint32_t* above;
+    int* cnt;
+};
+
+__device__ void band_topk(const double* bs, const int32_t* bid, int nb, int64_t kq, int32_t* ids, double* sc,
+                          const BandLds& L) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    unsigned long long ph = 0, mh = 0;
+    uint32_t pl = 0, ml = 0;
+    uint32_t need = (uint32_t)min<int64_t>(kq, nb);
+    if ((uint32_t)nb > need) {
+        for (int d = 0; d < 12; d++) {
+            for (int i = tid; i < 256; i += nt) L.hist[i] = 0u;
+            __syncthreads();
+            for (int i = tid; i < nb; i += nt) {
+                const unsigned long long h = (unsigned long long)__double_as_longlong(bs[i]);
+                const uint32_t l = ~(uint32_t)bid[i];
+                if ((h & mh) == ph && (l & ml) == pl) {
+                    const uint32_t dig = d < 8 ? (uint32_t)(h >> (56 - 8 * d)) & 255u : (l >> (88 - 8 * d)) & 255u;
+                    atomicAdd(&L.hist[dig], 1u);
+                }
+            }
+            __syncthreads();
+            if (tid < kWave) walk256(L.hist, need, L.d, L.above);
+            __syncthreads();
+            const int dsel = *L.d;
+            need -= *L.above;
+            const uint32_t hd = L.hist[dsel];
+            __syncthreads();
+            if (d < 8) {
+                ph |= (unsigned long long)dsel << (56 - 8 * d);
+                mh |= 255ull << (56 - 8 * d);
+            } else {
+                pl |= (uint32_t)dsel << (88 - 8 * d);  // id digits: bits 31..24, ..., 7..0
+                ml |= 255u << (88 - 8 * d);
+            }
+            if (hd == need) break;
+        }
+    }
+    if (tid == 0) *L.cnt = 0;
+    __syncthreads();
+    for (int i = tid; i < nb; i += nt) {
+        const unsigned long long h = (unsigned long long)__double_as_longlong(bs[i]);
+        const uint32_t l = ~(uint32_t)bid[i];
+        if (h > ph || (h == ph && l >= pl)) {
+            const int pos = atomicAdd(L.cnt, 1);
+            if (pos < kMaxK) {
+                L.wsc[pos] = h;
+                L.wid[pos] = bid[i];
+            }
+        }
+    }
+    __syncthreads();
+    const int m = min(*L.cnt, kMaxK);
+    for (int i = tid; i < m; i += nt) {
+        const unsigned long long si = L.wsc[i];
+        const int32_t di = L.wid[i];
+        int r = 0;
+        for (int j = 0; j < m; j++) {
+            const unsigned long long sj = L.wsc[j];
+            r += (sj > si) || (sj == si && L.wid[j] < di);
+        }
+        if (r < kq) {
+            ids[r] = di;
+            sc[r] = __longlong_as_double((long long)si);
+        }
     }
 }
 
@@ -243,6 +374,7 @@ __global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_
     __shared__ uint32_t sh_above;
     __shared__ int32_t sq_t[kMaxQueryNnz];
     __shared__ float sq_w[kMaxQueryNnz];
+    __shared__ int32_t band_wid[P == kBF16 ? kMaxK : 1];
     const int tid = threadIdx.x;
     const int ql = blockIdx.x, q = q0 + ql;
     SelState* st = state + ql;
@@ -350,50 +482,43 @@ __global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_
     const float sk = __uint_as_float((uint32_t)(sh_min >> 32));
     double* bs = band_s + (int64_t)ql * kCandCap;
     int32_t* bid = band_id + (int64_t)ql * kCandCap;
+    int nb = 0;
     if (sk == 0.0f) {
         // fewer than k docs share a term with the query: the k winners are every doc with a
-        // positive score plus the lowest-id zero-score docs; zeros are exact, positives are rescored
-        for (int i = tid; i < m; i += 1024) {
-            const unsigned long long c = sel[i];
-            const int32_t doc = (int32_t)(~(uint32_t)c);
-            bid[i] = doc;
-            bs[i] = (c >> 32) ? rescore_f64(ix, doc, sq_t, sq_w, nq) : 0.0;
+        // positive score plus the lowest-id zero-score docs (a zero approximate score is exact)
+        for (int i = tid; i < m; i += 1024) bid[i] = (int32_t)(~(uint32_t)sel[i]);
+        nb = m;
+    } else {
+        const double tau = band_tau(sk, qb.delta[q], qb.q_abs_err[q]);
+        const unsigned long long lo = st->lo;
+        const double lo_val = (double)__uint_as_float((uint32_t)(lo >> 32));
+        const bool inside = tau > 0.0 && (((uint32_t)lo == 0u) ? (lo_val <= tau) : (lo_val < tau));
+        if (!inside) {
+            if (tid == 0) {
+                st->need_band_pass = 1;
+                st->tau = tau;
+            }
+            return;
         }
-        if (tid == 0) st->band = m;
-        __threadfence_block();
+        if (tid == 0) sh_cnt = 0;
         __syncthreads();
-        rank_band(bs, bid, m, kq, ids, (double*)out_scores + (int64_t)q * kmax);
-        return;
-    }
-    const double tau = band_tau(sk, qb.delta[q], qb.q_abs_err[q]);
-    const unsigned long long lo = st->lo;
-    const double lo_val = (double)__uint_as_float((uint32_t)(lo >> 32));
-    const bool inside = tau > 0.0 && (((uint32_t)lo == 0u) ? (lo_val <= tau) : (lo_val < tau));
-    if (!inside) {
-        if (tid == 0) {
-            st->need_band_pass = 1;
-            st->tau = tau;
+        for (int i = tid; i < n; i += 1024) {
+            const unsigned long long c = C[i];
+            const double v = (double)__uint_as_float((uint32_t)(c >> 32));
+            if (v > 0.0 && v >= tau) bid[atomicAdd(&sh_cnt, 1)] = (int32_t)(~(uint32_t)c);
         }
-        return;
+        __syncthreads();
+        nb = sh_cnt;
     }
-    if (tid == 0) sh_cnt = 0;
+    __threadfence_block();
     __syncthreads();
-    for (int i = tid; i < n; i += 1024) {
-        const unsigned long long c = C[i];
-        const double v = (double)__uint_as_float((uint32_t)(c >> 32));
-        if (v > 0.0 && v >= tau) {
-            const int pos = atomicAdd(&sh_cnt, 1);
-            const int32_t doc = (int32_t)(~(uint32_t)c);
-            bid[pos] = doc;
-            bs[pos] = rescore_f64(ix, doc, sq_t, sq_w, nq);
-        }
-    }
-    __syncthreads();
-    const int nb = sh_cnt;
+    rescore_band(ix, bid, bs, nb, sq_t, sq_w, nq);
     if (tid == 0) st->band = nb;
     __threadfence_block();
     __syncthreads();
-    rank_band(bs, bid, nb, kq, ids, (double*)out_scores + (int64_t)q * kmax);
+    // sel (the approximate winners) is no longer needed: it holds the exact winners' scores
+    band_topk(bs, bid, nb, kq, ids, (double*)out_scores + (int64_t)q * kmax,
+              BandLds{hist, sel, band_wid, &sh_d, &sh_above, &sh_cnt});
 }
 
 __global__ __launch_bounds__(512) void k_band_filter(int32_t q0, int64_t N, const uint32_t* __restrict__ S,
@@ -428,6 +553,11 @@ __global__ __launch_bounds__(1024) void k_band_final(DevIndex ix, DevBatch qb, i
                                                      int32_t* __restrict__ out_ids, double* __restrict__ out_scores) {
     __shared__ int32_t sq_t[kMaxQueryNnz];
     __shared__ float sq_w[kMaxQueryNnz];
+    __shared__ uint32_t hist[256];
+    __shared__ unsigned long long wsc[kMaxK];
+    __shared__ int32_t wid[kMaxK];
+    __shared__ int sh_d, sh_cnt;
+    __shared__ uint32_t sh_above;
     const int ql = blockIdx.x, q = q0 + ql;
     SelState* st = state + ql;
     if (st->need_band_pass != 1) return;
@@ -451,10 +581,11 @@ __global__ __launch_bounds__(1024) void k_band_final(DevIndex ix, DevBatch qb, i
     const int nb = min(st->band, kCandCap);
     double* bs = band_s + (int64_t)ql * kCandCap;
     int32_t* bid = band_id + (int64_t)ql * kCandCap;
-    for (int i = tid; i < nb; i += 1024) bs[i] = rescore_f64(ix, bid[i], sq_t, sq_w, nq);
+    rescore_band(ix, bid, bs, nb, sq_t, sq_w, nq);
     __threadfence_block();
     __syncthreads();
-    rank_band(bs, bid, nb, kq, out_ids + (int64_t)q * qb.k_max, out_scores + (int64_t)q * qb.k_max);
+    band_topk(bs, bid, nb, kq, out_ids + (int64_t)q * qb.k_max, out_scores + (int64_t)q * qb.k_max,
+              BandLds{hist, wsc, wid, &sh_d, &sh_above, &sh_cnt});
 }
 
 __global__ void k_diag(int32_t q0, int32_t qt, const SelState* __restrict__ state, int32_t* __restrict__ diag) {

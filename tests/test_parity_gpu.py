@@ -72,7 +72,8 @@ def test_hand_worked_example(precision):
 
 
 @pytest.mark.parametrize("precision,tile_docs", [("fp32", 8192), ("fp32", 16384), ("u8", 8192), ("u8", 16384),
-                                                 ("u8", 32768), ("bf16", 8192)])
+                                                 ("u8", 32768), ("bf16", 8192), ("bf16", 16384),
+                                                 ("bf16", 32768)])
 @pytest.mark.parametrize("chunk", [64, 256, 1024])
 def test_dyadic_weights_are_exact_across_tiles(precision, tile_docs, chunk):
     # multiples of 1/16: every sum is exact, so fp32 scores must equal the fp64 oracle bit for bit
@@ -94,7 +95,8 @@ def test_dyadic_weights_are_exact_across_tiles(precision, tile_docs, chunk):
                 check_exact_f64(ids[q], sc[q], rid[q], rsc[q], "%s q%d" % (kernel, q))
 
 
-def test_fixed_point_tiles_reject_32768_docs():
+def test_fp32_tiles_reject_32768_docs():
+    # 32768 docs of 64-bit accumulators do not fit one CU's LDS
     gs = _gs()
     docs = random_rows(np.random.default_rng(2), 100, 20, 1, 5)
     idx = gs.Index.from_rows(docs, "fp32")
