@@ -158,15 +158,38 @@ __global__ __launch_bounds__(64) void k_refine_select(DevBatch qb, int32_t q0, i
 
 // Append every composite >= the query's threshold to its candidate buffer.
 // Each lane reads four consecutive scores with one 16-byte load (rows are
-// 64-aligned); the wavefront appends with one ballot + popcount per column.
+// 64-aligned). A wavefront reserves slots for its hits (ballot + popcount) in
+// a workgroup-local LDS stage, so the scan never waits on a global atomic; at
+// the end the workgroup takes one range of the query's buffer and copies the
+// stage out. Hits that find the stage full are appended to the global buffer
+// directly (slot from a global atomic), so any number of hits is handled.
+constexpr int kFilterStage = 4096;
+
+__device__ __forceinline__ void append_global(SelState* st, unsigned long long* C, bool take,
+                                              unsigned long long c, int lane) {
+    const unsigned long long m = __ballot(take);
+    if (m == 0) return;
+    int slot = 0;
+    if (lane == 0) slot = atomicAdd(&st->n_cand, __popcll(m));
+    slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
+    if (take) {
+        if (slot < kCandCap) C[slot] = c;
+        else st->overflow = 1;
+    }
+}
+
 __global__ __launch_bounds__(512) void k_filter(int32_t q0, int64_t N, const uint32_t* __restrict__ S, int64_t ld,
                                                 int per_block, SelState* __restrict__ state,
                                                 unsigned long long* __restrict__ cand) {
+    __shared__ unsigned long long stage[kFilterStage];
+    __shared__ int n_stage, g_base;
     const int ql = blockIdx.y;
     SelState* st = state + ql;
     if (st->resolved != 1) return;
     const unsigned long long lo = st->lo;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    if (tid == 0) n_stage = 0;
+    __syncthreads();
     const int64_t d0 = (int64_t)blockIdx.x * per_block, d1 = min(N, d0 + per_block);  // per_block % 256 == 0
     const uint32_t* Sq = S + (int64_t)ql * ld;
     unsigned long long* C = cand + (int64_t)ql * kCandCap;
@@ -182,13 +205,20 @@ __global__ __launch_bounds__(512) void k_filter(int32_t q0, int64_t N, const uin
             const unsigned long long m = __ballot(take);
             if (m == 0) continue;
             int slot = 0;
-            if (lane == 0) slot = atomicAdd(&st->n_cand, __popcll(m));
+            if (lane == 0) slot = atomicAdd(&n_stage, __popcll(m));
             slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
-            if (take) {
-                if (slot < kCandCap) C[slot] = c;
-                else st->overflow = 1;
-            }
+            if (take && slot < kFilterStage) stage[slot] = c;
+            append_global(st, C, take && slot >= kFilterStage, c, lane);
         }
+    }
+    __syncthreads();
+    const int n = min(n_stage, kFilterStage);
+    if (tid == 0) g_base = n ? atomicAdd(&st->n_cand, n) : 0;
+    __syncthreads();
+    const int base = g_base;
+    for (int i = tid; i < n; i += 512) {
+        if (base + i < kCandCap) C[base + i] = stage[i];
+        else st->overflow = 1;
     }
 }
 
