@@ -306,17 +306,54 @@ struct gs_index_s {
     }
 };
 
+// Byte offsets of a batch's arrays inside its one device allocation (and the
+// pinned host stage of the same layout): the per-query arrays first (copied
+// whole on every update), then the per-term arrays (copied up to the terms in use).
+struct BatchLayout {
+    size_t rp = 0, k = 0, fs = 0, delta = 0, scale = 0, err = 0, work = 0, diag = 0, head = 0;
+    size_t term = 0, w = 0, w8 = 0, fx = 0, total = 0;
+    BatchLayout(size_t nq, size_t nz) {
+        size_t at = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = at;
+            at = (at + std::max<size_t>(bytes, 8) + 255) / 256 * 256;
+            return o;
+        };
+        rp = take((nq + 1) * 8);
+        k = take(nq * 4);
+        fs = take(nq * 4);
+        delta = take(nq * 4);
+        scale = take(nq * 8);
+        err = take(nq * 8);
+        work = take(nq * 8);
+        diag = take(nq * 16);
+        head = at;
+        term = take(nz * 4);
+        w = take(nz * 4);
+        w8 = take(nz * 4);
+        fx = take(nz * 8);
+        total = at;
+    }
+};
+
 struct gs_batch_s {
     gs_index index = nullptr;          // borrowed: must outlive searches, not needed to free the batch
     int device = 0;                    // device holding the batch's memory
     int32_t n_queries = 0, k_max = 0;  // capacity in queries (launch shapes use it)
     int64_t q_nnz = 0;                 // capacity in query terms
     int32_t n_active = 0;              // queries set by the last update
-    std::vector<void*> allocs;
+    BatchLayout lay{0, 0};
+    uint8_t* dmem = nullptr;    // device: every array of the batch
+    uint8_t* stage = nullptr;   // pinned host copy of the same layout (update staging)
+    hipEvent_t copied = nullptr;  // recorded after the last update's copies
+    bool copy_pending = false;
     DevBatch dev{};
-    int32_t* diag = nullptr;  // [n_queries * 4]
+    int32_t* diag = nullptr;  // [n_queries * 4] (inside dmem)
     ~gs_batch_s() {
-        for (void* p : allocs) (void)hipFree(p);
+        if (copy_pending) (void)hipEventSynchronize(copied);
+        if (copied) (void)hipEventDestroy(copied);
+        if (dmem) (void)hipFree(dmem);
+        if (stage) (void)hipHostFree(stage);
     }
 };
 
@@ -637,38 +674,32 @@ int32_t gs_batch_reserve(gs_index ix, int32_t max_queries, int64_t max_nnz, int3
         return code;
     };
     const size_t nq = (size_t)max_queries, nz = (size_t)max_nnz;
-    size_t bytes = 0;
-    int32_t rc;
+    b->lay = BatchLayout(nq, nz);
+    const BatchLayout& L = b->lay;
+    {
+        hipError_t e = hipMalloc((void**)&b->dmem, L.total);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&b->stage, L.total, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return done(fail(e == hipErrorOutOfMemory ? GS_ENOMEM : GS_EHIP,
+                             std::string("batch allocation: ") + hipGetErrorString(e)));
+    }
+    uint8_t* m = b->dmem;
     DevBatch& d = b->dev;
-    int64_t *rp = nullptr, *work = nullptr;
-    int32_t *t = nullptr, *w8 = nullptr, *k = nullptr, *fs = nullptr;
-    float *w = nullptr, *delta = nullptr;
-    double *fx = nullptr, *scale = nullptr, *err = nullptr;
-    if ((rc = dev_upload<int64_t>(b->allocs, bytes, nullptr, nq + 1, &rp, nullptr))) return done(rc);
-    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nz, &t, nullptr))) return done(rc);
-    if ((rc = dev_upload<float>(b->allocs, bytes, nullptr, nz, &w, nullptr))) return done(rc);
-    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nz, &w8, nullptr))) return done(rc);
-    if ((rc = dev_upload<double>(b->allocs, bytes, nullptr, nz, &fx, nullptr))) return done(rc);
-    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nq, &k, nullptr))) return done(rc);
-    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nq, &fs, nullptr))) return done(rc);
-    if ((rc = dev_upload<float>(b->allocs, bytes, nullptr, nq, &delta, nullptr))) return done(rc);
-    if ((rc = dev_upload<double>(b->allocs, bytes, nullptr, nq, &scale, nullptr))) return done(rc);
-    if ((rc = dev_upload<double>(b->allocs, bytes, nullptr, nq, &err, nullptr))) return done(rc);
-    if ((rc = dev_upload<int64_t>(b->allocs, bytes, nullptr, nq, &work, nullptr))) return done(rc);
-    if ((rc = dev_upload<int32_t>(b->allocs, bytes, nullptr, nq * 4, &b->diag, nullptr))) return done(rc);
     d.n_queries = max_queries;
     d.k_max = k_max;
-    d.q_row_ptr = rp;
-    d.q_term = t;
-    d.q_w = w;
-    d.q_w8 = w8;
-    d.q_fx = fx;
-    d.k = k;
-    d.first_shift = fs;
-    d.delta = delta;
-    d.q_scale = scale;
-    d.q_abs_err = err;
-    d.q_work = work;
+    d.q_row_ptr = (const int64_t*)(m + L.rp);
+    d.q_term = (const int32_t*)(m + L.term);
+    d.q_w = (const float*)(m + L.w);
+    d.q_w8 = (const int32_t*)(m + L.w8);
+    d.q_fx = (const double*)(m + L.fx);
+    d.k = (const int32_t*)(m + L.k);
+    d.first_shift = (const int32_t*)(m + L.fs);
+    d.delta = (const float*)(m + L.delta);
+    d.q_scale = (const double*)(m + L.scale);
+    d.q_abs_err = (const double*)(m + L.err);
+    d.q_work = (const int64_t*)(m + L.work);
+    b->diag = (int32_t*)(m + L.diag);
     // an empty batch until the first update: every slot is a query with no terms and k = 0
     std::vector<int64_t> zero_rp(nq + 1, 0);
     int32_t rc2 = gs_batch_update(b, zero_rp.data(), 0, nullptr, nullptr, 0, nullptr, nullptr);
@@ -677,8 +708,12 @@ int32_t gs_batch_reserve(gs_index ix, int32_t max_queries, int64_t max_nnz, int3
     return GS_OK;
 }
 
-int32_t gs_batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
-                        const float* q_weights, int64_t q_nnz, const int32_t* k, void* hip_stream) {
+}  // extern "C"
+
+namespace gs {
+
+int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
+                     const float* q_weights, int64_t q_nnz, const int32_t* k, void* hip_stream, bool wait) {
     g_err.clear();
     if (!b) return fail(GS_EINVAL, "batch is null");
     gs_index ix = b->index;
@@ -692,23 +727,40 @@ int32_t gs_batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries,
     int32_t rc = check_rows(r, q_nnz, ix->vocab, kMaxQueryNnz, "queries");
     if (rc != GS_OK) return rc;
     const int32_t cap = b->n_queries;
+    DeviceGuard g(ix->device);
+    // the stage may still be read by the previous update's copies
+    if (b->copy_pending) {
+        GS_HIP(hipEventSynchronize(b->copied));
+        b->copy_pending = false;
+    }
+    const BatchLayout& L = b->lay;
+    uint8_t* h = b->stage;
+    int64_t* rp = (int64_t*)(h + L.rp);
+    int32_t* kk = (int32_t*)(h + L.k);
+    int32_t* fshift = (int32_t*)(h + L.fs);
+    float* delta = (float*)(h + L.delta);
+    double* qscale = (double*)(h + L.scale);
+    double* qerr = (double*)(h + L.err);
+    int64_t* qwork = (int64_t*)(h + L.work);
+    int32_t* w8 = (int32_t*)(h + L.w8);
+    double* qfx = (double*)(h + L.fx);
     // slots past n_queries become empty queries with k = 0 (no work, padding-only rows)
-    std::vector<int64_t> rp((size_t)cap + 1, q_nnz);
-    for (int32_t q = 0; q <= n_queries; q++) rp[(size_t)q] = q_row_ptr ? q_row_ptr[q] : 0;
-    std::vector<int32_t> kk((size_t)cap, 0), w8((size_t)std::max<int64_t>(q_nnz, 1), 0), fshift((size_t)cap);
-    for (int32_t q = 0; q < n_queries; q++) kk[(size_t)q] = k[q];
-    std::vector<double> qfx((size_t)std::max<int64_t>(q_nnz, 1), 0.0);
-    std::vector<float> delta((size_t)cap);
-    std::vector<double> qscale((size_t)cap), qerr((size_t)cap);
-    std::vector<int64_t> qwork((size_t)cap, 0);
+    for (int32_t q = 0; q <= cap; q++) rp[q] = q <= n_queries ? (q_row_ptr ? q_row_ptr[q] : 0) : q_nnz;
+    for (int32_t q = 0; q < cap; q++) kk[q] = q < n_queries ? k[q] : 0;
+    std::memset(h + L.diag, 0, (size_t)cap * 16);
+    if (q_nnz > 0) {
+        std::memcpy(h + L.term, r.term, (size_t)q_nnz * 4);
+        std::memcpy(h + L.w, r.w, (size_t)q_nnz * 4);
+    }
     for (int32_t q = 0; q < cap; q++) {
         uint64_t maxs = 0;
         double maxprod = 0.0, sumprod = 0.0;
-        const int64_t m = rp[(size_t)q + 1] - rp[(size_t)q];
-        for (int64_t j = rp[(size_t)q]; j < rp[(size_t)q + 1]; j++) {
-            qwork[(size_t)q] += ix->term_len[(size_t)r.term[j]];
-            w8[(size_t)j] = q8(r.w[j]);
-            maxs += (uint64_t)w8[(size_t)j] * 255u;
+        const int64_t m = rp[q + 1] - rp[q];
+        qwork[q] = 0;
+        for (int64_t j = rp[q]; j < rp[q + 1]; j++) {
+            qwork[q] += ix->term_len[(size_t)r.term[j]];
+            w8[j] = q8(r.w[j]);
+            maxs += (uint64_t)w8[j] * 255u;
             const double pm = (double)r.w[j] * (double)ix->term_max[(size_t)r.term[j]];
             maxprod = std::max(maxprod, pm);
             sumprod += pm;  // bound on any doc's score: the largest stored weight of every query term
@@ -716,9 +768,9 @@ int32_t gs_batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries,
         if (ix->precision == kU8) {
             int hb = 0;
             while (hb < 64 && (maxs >> hb) != 0) hb++;
-            fshift[(size_t)q] = 32 + std::max(hb, kHistBits) - kHistBits;
+            fshift[q] = 32 + std::max(hb, kHistBits) - kHistBits;
         } else {
-            fshift[(size_t)q] = kFirstShiftFloat;
+            fshift[q] = kFirstShiftFloat;
         }
         // fixed point in units of 2^-F. fp32 (64-bit sums): every product of this query below
         // 2^51 units, so a sum of at most 256 products stays below 2^59. bf16 (32-bit sums):
@@ -735,36 +787,43 @@ int32_t gs_batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries,
             F = 51 - ex;
         }
         F = std::min(1000, std::max(-1000, F));
-        qscale[(size_t)q] = std::ldexp(1.0, -F);
+        qscale[q] = std::ldexp(1.0, -F);
         // each product is within half a unit (or, raised from 0 to 1, within one unit) of exact
-        qerr[(size_t)q] = (double)(m + 1) * std::ldexp(1.0, -F) * (1.0 + 1e-6);
-        for (int64_t j = rp[(size_t)q]; j < rp[(size_t)q + 1]; j++) qfx[(size_t)j] = std::ldexp((double)r.w[j], F);
+        qerr[q] = (double)(m + 1) * std::ldexp(1.0, -F) * (1.0 + 1e-6);
+        for (int64_t j = rp[q]; j < rp[q + 1]; j++) qfx[j] = std::ldexp((double)r.w[j], F);
         // bf16 form: relative error of a stored weight (2^-8) and of the fp32 score (2^-24, with margin)
-        delta[(size_t)q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -23)) - 1.0) * (1.0 + 1e-6));
+        delta[q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -23)) - 1.0) * (1.0 + 1e-6));
     }
-    DeviceGuard g(ix->device);
+    // copies on the caller's stream, ordered after the searches already enqueued on it
     hipStream_t s = (hipStream_t)hip_stream;
-    // searches already enqueued on this stream may still read the batch
-    GS_HIP(hipStreamSynchronize(s));
-    const DevBatch& d = b->dev;
-    auto up = [&](const void* dst, const void* src, size_t bytes) -> hipError_t {
-        return bytes ? hipMemcpy((void*)dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    auto up = [&](size_t off, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(b->dmem + off, h + off, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
     };
-    hipError_t e = up(d.q_row_ptr, rp.data(), rp.size() * 8);
-    if (e == hipSuccess) e = up(d.q_term, r.term, (size_t)q_nnz * 4);
-    if (e == hipSuccess) e = up(d.q_w, r.w, (size_t)q_nnz * 4);
-    if (e == hipSuccess) e = up(d.q_w8, w8.data(), (size_t)q_nnz * 4);
-    if (e == hipSuccess) e = up(d.q_fx, qfx.data(), (size_t)q_nnz * 8);
-    if (e == hipSuccess) e = up(d.k, kk.data(), (size_t)cap * 4);
-    if (e == hipSuccess) e = up(d.first_shift, fshift.data(), (size_t)cap * 4);
-    if (e == hipSuccess) e = up(d.delta, delta.data(), (size_t)cap * 4);
-    if (e == hipSuccess) e = up(d.q_scale, qscale.data(), (size_t)cap * 8);
-    if (e == hipSuccess) e = up(d.q_abs_err, qerr.data(), (size_t)cap * 8);
-    if (e == hipSuccess) e = up(d.q_work, qwork.data(), (size_t)cap * 8);
-    if (e == hipSuccess) e = hipMemset(b->diag, 0, (size_t)std::max(cap, 1) * 16);
+    hipError_t e = up(0, L.head);
+    if (e == hipSuccess) e = up(L.term, (size_t)q_nnz * 4);
+    if (e == hipSuccess) e = up(L.w, (size_t)q_nnz * 4);
+    if (e == hipSuccess) e = up(L.w8, (size_t)q_nnz * 4);
+    if (e == hipSuccess) e = up(L.fx, (size_t)q_nnz * 8);
+    if (e == hipSuccess) e = hipEventRecord(b->copied, s);
+    if (e == hipSuccess) {
+        b->copy_pending = true;
+        if (wait) {
+            e = hipEventSynchronize(b->copied);
+            if (e == hipSuccess) b->copy_pending = false;
+        }
+    }
     if (e != hipSuccess) return fail(GS_EHIP, std::string("batch upload: ") + hipGetErrorString(e));
     b->n_active = n_queries;
     return GS_OK;
+}
+
+}  // namespace gs
+
+extern "C" {
+
+int32_t gs_batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
+                        const float* q_weights, int64_t q_nnz, const int32_t* k, void* hip_stream) {
+    return gs::batch_update(b, q_row_ptr, n_queries, q_term_ids, q_weights, q_nnz, k, hip_stream, true);
 }
 
 int32_t gs_batch_create(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries, const int32_t* q_term_ids,
@@ -861,9 +920,11 @@ int32_t plan_search(gs_index ix, gs_batch b, size_t workspace_bytes_, const gs_s
 }
 
 // Enqueue the whole search on stream s (no host synchronisation; capturable).
-int32_t enqueue_search(gs_index ix, gs_batch b, void* workspace, int32_t qt, const ScoreOpts& so, int32_t* out_ids,
-                       void* out_scores, hipStream_t s, bool timing) {
-    const int32_t nq = b->n_queries;
+// Queries [0, nq) are searched; output rows [nq, capacity) are written as padding
+// (id -1, score 0). A direct search passes the queries of the last update, a
+// graph the whole capacity (it is replayed after updates of any size).
+int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int32_t qt, const ScoreOpts& so,
+                       int32_t* out_ids, void* out_scores, hipStream_t s, bool timing) {
     Workspace ws;
     carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
     (void)hipGetLastError();  // launches below report their own status; drop any earlier, unrelated one
@@ -883,6 +944,15 @@ int32_t enqueue_search(gs_index ix, gs_batch b, void* workspace, int32_t qt, con
             e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s);
             rec.end(s);
         }
+        if (e != hipSuccess)
+            return fail(GS_EHIP, std::string("launch of ") + g_failed_launch + ": " + hipGetErrorString(e));
+    }
+    if (nq < b->n_queries) {
+        const int64_t rows = (int64_t)(b->n_queries - nq) * b->k_max;
+        const int64_t words = ix->precision == kBF16 ? 2 : 1;
+        hipError_t e = launch_fill(out_ids + (int64_t)nq * b->k_max, rows, 0xFFFFFFFFu, s);
+        if (e == hipSuccess)
+            e = launch_fill((uint32_t*)out_scores + (int64_t)nq * b->k_max * words, rows * words, 0u, s);
         if (e != hipSuccess)
             return fail(GS_EHIP, std::string("launch of ") + g_failed_launch + ": " + hipGetErrorString(e));
     }
@@ -914,7 +984,7 @@ int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspa
     if (!out_ids || !out_scores) return fail(GS_EINVAL, "null output");
     if (!workspace) return fail(GS_EINVAL, "null workspace");
     DeviceGuard g(ix->device);
-    return enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, (hipStream_t)hip_stream, true);
+    return enqueue_search(ix, b, b->n_active, workspace, qt, so, out_ids, out_scores, (hipStream_t)hip_stream, true);
 }
 
 int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspace_bytes_, int32_t* out_ids,
@@ -931,7 +1001,7 @@ int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspa
     DeviceGuard g(ix->device);
     hipStream_t s = (hipStream_t)hip_stream;
     // one eager run first: one-time kernel attributes and occupancy queries happen outside the capture
-    rc = enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, s, false);
+    rc = enqueue_search(ix, b, b->n_queries, workspace, qt, so, out_ids, out_scores, s, false);
     if (rc != GS_OK) return rc;
     GS_HIP(hipStreamSynchronize(s));
     gs_graph gr = new (std::nothrow) gs_graph_s();
@@ -946,7 +1016,7 @@ int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspa
         delete gr;
         return fail(GS_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
-    rc = enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, cs, false);
+    rc = enqueue_search(ix, b, b->n_queries, workspace, qt, so, out_ids, out_scores, cs, false);
     e = hipStreamEndCapture(cs, &gr->graph);
     (void)hipStreamDestroy(cs);
     if (rc != GS_OK) {
@@ -998,11 +1068,11 @@ int32_t gs_autotune(gs_index ix, gs_batch b, void* workspace, size_t workspace_b
         int32_t qt = 1;
         rc = plan_search(ix, b, workspace_bytes_, &cand[i], &so, &qt);
         if (rc != GS_OK) break;
-        rc = enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, s, false);  // untimed
+        rc = enqueue_search(ix, b, b->n_active, workspace, qt, so, out_ids, out_scores, s, false);  // untimed
         if (rc != GS_OK) break;
         he = hipEventRecord(e0, s);
         for (int r = 0; r < reps && rc == GS_OK && he == hipSuccess; r++)
-            rc = enqueue_search(ix, b, workspace, qt, so, out_ids, out_scores, s, false);
+            rc = enqueue_search(ix, b, b->n_active, workspace, qt, so, out_ids, out_scores, s, false);
         if (he == hipSuccess) he = hipEventRecord(e1, s);
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.0f;

@@ -7,6 +7,8 @@
 
 #include <string>
 
+struct gs_batch_s;
+
 namespace gs {
 
 constexpr int kWave = 64;             // CDNA wavefront
@@ -118,6 +120,13 @@ struct ScoreOpts {
     int group;
 };
 
+// Upload a query batch (gs_batch_update). With wait == false it returns once the
+// copies are enqueued on hip_stream (staged in pinned memory), for callers that
+// search on that same stream.
+int32_t batch_update(struct ::gs_batch_s* b, const int64_t* q_row_ptr, int32_t n_queries,
+                     const int32_t* q_term_ids, const float* q_weights, int64_t q_nnz, const int32_t* k,
+                     void* hip_stream, bool wait);
+
 // ---- launchers (gs_score.hip) ----
 hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s);
 hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
@@ -129,6 +138,7 @@ hipError_t launch_score_docpar(const DevIndex& ix, const DevBatch& qb, int32_t q
 hipError_t launch_hist1(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                         const Workspace& ws, hipStream_t s);
 hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s);
+hipError_t launch_fill(void* p, int64_t n_words, uint32_t v, hipStream_t s);  // p[0..n) = v (a kernel, capturable)
 
 // ---- launchers (gs_topk.hip) ----
 hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,

@@ -213,6 +213,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const int q = q0 + ql;
+    if (qb.k[q] == 0) return;  // nothing is selected for it (also every padding slot of a batch)
     const int64_t N = ix.n_docs;
     const int64_t base = tile << TS;
     const int tile_n = (int)min((int64_t)TILE, N - base);
@@ -562,13 +563,7 @@ __global__ __launch_bounds__(256) void k_copy16(uint4* __restrict__ dst, const u
         dst[i] = src[i];
 }
 
-hipError_t fill_u32(void* p, int64_t n_words, hipStream_t s) {
-    if (n_words <= 0) return hipSuccess;
-    const int64_t blocks = std::min<int64_t>((n_words + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n_words, 0u);
-    GS_CHECK_LAUNCH("k_fill_u32");
-    return hipSuccess;
-}
+hipError_t fill_u32(void* p, int64_t n_words, hipStream_t s) { return launch_fill(p, n_words, 0u, s); }
 
 template <typename F>
 hipError_t by_precision(int p, F f) {
@@ -641,6 +636,14 @@ hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32
 }  // namespace
 
 int64_t score_ld(int64_t n_docs) { return (n_docs + 63) / 64 * 64; }
+
+hipError_t launch_fill(void* p, int64_t n_words, uint32_t v, hipStream_t s) {
+    if (n_words <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n_words + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n_words, v);
+    GS_CHECK_LAUNCH("k_fill_u32");
+    return hipSuccess;
+}
 
 hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s) {
     if (n16 <= 0) return hipSuccess;

@@ -103,8 +103,9 @@ void gs_server_s::launch(Slot& s) {
         rp[(size_t)i + 1] = (int64_t)terms.size();
         k[(size_t)i] = r.k;
     }
-    int32_t rc = gs_batch_update(s.batch, rp.data(), n, terms.data(), w.data(), (int64_t)terms.size(), k.data(),
-                                 s.stream);
+    // the copies are staged in pinned memory and ordered before the search on the slot's stream
+    int32_t rc = gs::batch_update(s.batch, rp.data(), n, terms.data(), w.data(), (int64_t)terms.size(), k.data(),
+                                  s.stream, false);
     if (rc == GS_OK)
         rc = gs_search_batch(index, s.batch, s.ws, s.ws_bytes, s.d_ids, s.d_scores, &opts.search, s.stream);
     hipError_t e = hipSuccess;
