@@ -280,3 +280,32 @@ def test_full_scale_sampled(full, precision, kernel):
             assert np.max(np.abs(sc[q] - f) / f) < 1e-5
         assert np.all(np.diff(sc[q]) <= 0) and np.unique(ids[q]).shape[0] == 1000
     idx.close()
+
+
+@pytest.mark.parametrize("kernel", ["tiled", "shared"])
+def test_bf16_fixed_point_headroom(kernel):
+    # bf16 scores are summed in 32-bit fixed point, scaled per query so that the largest possible
+    # sum (every query term at its largest stored weight) stays below 2^32 units. Docs that reach
+    # that largest sum exactly must not wrap around: they are the top of the answer, and the
+    # rescored result must equal the fp64 oracle's.
+    gs = _gs()
+    rng = np.random.default_rng(21)
+    V = 2000
+    q_terms = np.sort(rng.choice(V, 250, replace=False)).astype(np.int32)
+    rows = []
+    for d in range(20_000):
+        if d % 997 == 0:  # every query term at 3.0, the largest weight of each of its lists
+            rows.append([(int(t), 3.0) for t in q_terms])
+        else:
+            n = int(rng.integers(5, 60))
+            t = np.sort(rng.choice(V, n, replace=False))
+            rows.append([(int(a), float(w)) for a, w in zip(t, rng.uniform(0.01, 2.9, n))])
+    docs = csr(rows, V)
+    qs = csr([[(int(t), 3.0) for t in q_terms], [(int(t), float(w)) for t, w in zip(q_terms, rng.uniform(0.5, 3.0, 250))]], V)
+    rid, rsc = oracle.topk_f64(docs, qs, 100)
+    full = list(range(0, 20_000, 997))
+    assert rsc[0, 0] == 250 * 9.0 and sorted(rid[0][:len(full)].tolist()) == full
+    assert sorted(rid[1][:len(full)].tolist()) == full
+    ids, sc, _ = _run(gs, docs, qs, 100, "bf16", kernel, tile_docs=32768)
+    for q in range(qs.n_rows):
+        check_exact_f64(ids[q], sc[q], rid[q], rsc[q], "headroom q%d" % q)
