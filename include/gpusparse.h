@@ -243,10 +243,15 @@ int32_t gs_search(gs_index index, const int64_t* q_row_ptr, int32_t n_queries,
  * hipGraph form of gs_search_batch: the full launch sequence for this batch
  * (at its capacity), workspace and outputs is run once on hip_stream and then
  * captured into a graph; gs_graph_launch replays it on any stream. The graph
- * holds the pointers given here: they must stay valid, and the batch may be
- * refilled with gs_batch_update between launches. No memset or host work is
- * captured (buffers are cleared by kernels). Errors: as gs_search_batch, plus
- * GS_EHIP for capture or instantiation failures.
+ * holds the pointers given here (the batch included): they must stay valid,
+ * and the batch may be refilled with gs_batch_update between launches. No
+ * memset or host work is captured (buffers are cleared by kernels). The
+ * fixed-point kernels come in two forms, with and without the raise of a
+ * positive product that rounds to 0 units; the graph captures the form the
+ * batch needs at capture time, and a launch after a refill that needs the
+ * other form enqueues the same search directly instead (same results).
+ * Errors: as gs_search_batch, plus GS_EHIP for capture or instantiation
+ * failures.
  */
 typedef struct gs_graph_s* gs_graph;
 int32_t gs_graph_create(gs_index index, gs_batch batch, void* workspace, size_t workspace_bytes,

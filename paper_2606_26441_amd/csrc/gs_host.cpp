@@ -11,6 +11,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <limits>
 #include <thread>
 #include <vector>
 
@@ -298,6 +299,7 @@ struct gs_index_s {
     uint32_t flags = 0;
     size_t bytes = 0;
     std::vector<float> term_max;  // largest stored weight of each term (value of the stored form)
+    std::vector<float> term_min;  // smallest positive stored weight of each term (+inf if none)
     std::vector<int32_t> term_len;  // postings per term (host copy, for work estimates)
     std::vector<void*> allocs;
     DevIndex dev{};
@@ -311,7 +313,7 @@ struct gs_index_s {
 // whole on every update), then the per-term arrays (copied up to the terms in use).
 struct BatchLayout {
     size_t rp = 0, k = 0, fs = 0, delta = 0, scale = 0, err = 0, work = 0, diag = 0, head = 0;
-    size_t term = 0, w = 0, w8 = 0, fx = 0, total = 0;
+    size_t term = 0, w = 0, w8 = 0, fx = 0, bump = 0, total = 0;
     BatchLayout(size_t nq, size_t nz) {
         size_t at = 0;
         auto take = [&](size_t bytes) {
@@ -332,6 +334,7 @@ struct BatchLayout {
         w = take(nz * 4);
         w8 = take(nz * 4);
         fx = take(nz * 8);
+        bump = take(nz * 4);
         total = at;
     }
 };
@@ -342,6 +345,7 @@ struct gs_batch_s {
     int32_t n_queries = 0, k_max = 0;  // capacity in queries (launch shapes use it)
     int64_t q_nnz = 0;                 // capacity in query terms
     int32_t n_active = 0;              // queries set by the last update
+    bool any_raise = true;             // some product of the batch may round to 0 units (fixed point)
     BatchLayout lay{0, 0};
     uint8_t* dmem = nullptr;    // device: every array of the batch
     uint8_t* stage = nullptr;   // pinned host copy of the same layout (update staging)
@@ -360,14 +364,18 @@ struct gs_batch_s {
 namespace {
 
 template <typename T>
-int32_t dev_upload(std::vector<void*>& allocs, size_t& bytes, const T* host, size_t n, T** out, hipStream_t s) {
+int32_t dev_upload(std::vector<void*>& allocs, size_t& bytes, const T* host, size_t n, T** out, hipStream_t s,
+                   size_t slack = 0) {
     *out = nullptr;
+    const size_t copy = n;
     if (n == 0) n = 1;  // keep a valid pointer for empty arrays
+    n += slack;         // zeroed entries past the end
     void* p = nullptr;
     GS_HIP(hipMalloc(&p, n * sizeof(T)));
     allocs.push_back(p);
     bytes += n * sizeof(T);
-    if (host) GS_HIP(hipMemcpyAsync(p, host, n * sizeof(T), hipMemcpyHostToDevice, s));
+    if (host && copy) GS_HIP(hipMemcpyAsync(p, host, copy * sizeof(T), hipMemcpyHostToDevice, s));
+    if (n > copy) GS_HIP(hipMemsetAsync((T*)p + copy, 0, (n - copy) * sizeof(T), s));
     *out = (T*)p;
     return GS_OK;
 }
@@ -559,6 +567,17 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     for (int32_t v = 0; v < vocab_size; v++)
         for (int64_t k = L.term_off[(size_t)v] / kBlock; k < L.term_off[(size_t)v + 1] / kBlock; k++)
             ix->term_max[(size_t)v] = std::max(ix->term_max[(size_t)v], L.blk_max[(size_t)k]);
+    ix->term_min.assign((size_t)vocab_size, std::numeric_limits<float>::infinity());
+    parallel_for(vocab_size, [&](int, int64_t a, int64_t b) {
+        for (int64_t v = a; v < b; v++) {
+            float m = std::numeric_limits<float>::infinity();
+            for (int64_t i = L.term_off[(size_t)v]; i < L.term_off[(size_t)v] + L.term_len[(size_t)v]; i++) {
+                const float w = stored_weight(L, i);
+                if (w > 0.0f) m = std::min(m, w);
+            }
+            ix->term_min[(size_t)v] = m;
+        }
+    });
     DevIndex& d = ix->dev;
     d.n_docs = n_docs;
     d.vocab = vocab_size;
@@ -595,20 +614,20 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
                     low[(size_t)i] = (uint16_t)((uint32_t)L.post_doc[(size_t)i] & 0xFFFFu);
             });
         for (auto& x : th) x.join();
-        if ((rc = dev_upload(ix->allocs, ix->bytes, low.data(), low.size(), &lo, s))) return done(rc);
+        if ((rc = dev_upload(ix->allocs, ix->bytes, low.data(), low.size(), &lo, s, kPostSlack))) return done(rc);
         d.post_lo = lo;
     }
     if (precision == kFP32) {
         float* p = nullptr;
-        if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_f32.data(), L.w_f32.size(), &p, s))) return done(rc);
+        if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_f32.data(), L.w_f32.size(), &p, s, kPostSlack))) return done(rc);
         d.post_w = p;
     } else if (precision == kBF16) {
         uint16_t* p = nullptr;
-        if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_bf16.data(), L.w_bf16.size(), &p, s))) return done(rc);
+        if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_bf16.data(), L.w_bf16.size(), &p, s, kPostSlack))) return done(rc);
         d.post_w = p;
     } else {
         uint8_t* p = nullptr;
-        if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_u8.data(), L.w_u8.size(), &p, s))) return done(rc);
+        if ((rc = dev_upload(ix->allocs, ix->bytes, L.w_u8.data(), L.w_u8.size(), &p, s, kPostSlack))) return done(rc);
         d.post_w = p;
     }
     float* blk_max = nullptr;
@@ -693,6 +712,7 @@ int32_t gs_batch_reserve(gs_index ix, int32_t max_queries, int64_t max_nnz, int3
     d.q_w = (const float*)(m + L.w);
     d.q_w8 = (const int32_t*)(m + L.w8);
     d.q_fx = (const double*)(m + L.fx);
+    d.q_bump = (const int32_t*)(m + L.bump);
     d.k = (const int32_t*)(m + L.k);
     d.first_shift = (const int32_t*)(m + L.fs);
     d.delta = (const float*)(m + L.delta);
@@ -744,6 +764,7 @@ int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, co
     int64_t* qwork = (int64_t*)(h + L.work);
     int32_t* w8 = (int32_t*)(h + L.w8);
     double* qfx = (double*)(h + L.fx);
+    int32_t* qbump = (int32_t*)(h + L.bump);
     // slots past n_queries become empty queries with k = 0 (no work, padding-only rows)
     for (int32_t q = 0; q <= cap; q++) rp[q] = q <= n_queries ? (q_row_ptr ? q_row_ptr[q] : 0) : q_nnz;
     for (int32_t q = 0; q < cap; q++) kk[q] = q < n_queries ? k[q] : 0;
@@ -790,10 +811,16 @@ int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, co
         qscale[q] = std::ldexp(1.0, -F);
         // each product is within half a unit (or, raised from 0 to 1, within one unit) of exact
         qerr[q] = (double)(m + 1) * std::ldexp(1.0, -F) * (1.0 + 1e-6);
-        for (int64_t j = rp[q]; j < rp[q + 1]; j++) qfx[j] = std::ldexp((double)r.w[j], F);
+        for (int64_t j = rp[q]; j < rp[q + 1]; j++) {
+            qfx[j] = std::ldexp((double)r.w[j], F);
+            // a positive product of this term can round to 0 units only if its smallest one is below 1 unit
+            qbump[j] = !(qfx[j] * (double)ix->term_min[(size_t)r.term[j]] >= 1.0);
+        }
         // bf16 form: relative error of a stored weight (2^-8) and of the fp32 score (2^-24, with margin)
         delta[q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -23)) - 1.0) * (1.0 + 1e-6));
     }
+    b->any_raise = false;
+    for (int64_t j = 0; j < rp[n_queries]; j++) b->any_raise |= qbump[j] != 0;
     // copies on the caller's stream, ordered after the searches already enqueued on it
     hipStream_t s = (hipStream_t)hip_stream;
     auto up = [&](size_t off, size_t bytes) -> hipError_t {
@@ -804,6 +831,7 @@ int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, co
     if (e == hipSuccess) e = up(L.w, (size_t)q_nnz * 4);
     if (e == hipSuccess) e = up(L.w8, (size_t)q_nnz * 4);
     if (e == hipSuccess) e = up(L.fx, (size_t)q_nnz * 8);
+    if (e == hipSuccess) e = up(L.bump, (size_t)q_nnz * 4);
     if (e == hipSuccess) e = hipEventRecord(b->copied, s);
     if (e == hipSuccess) {
         b->copy_pending = true;
@@ -923,8 +951,10 @@ int32_t plan_search(gs_index ix, gs_batch b, size_t workspace_bytes_, const gs_s
 // Queries [0, nq) are searched; output rows [nq, capacity) are written as padding
 // (id -1, score 0). A direct search passes the queries of the last update, a
 // graph the whole capacity (it is replayed after updates of any size).
-int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int32_t qt, const ScoreOpts& so,
-                       int32_t* out_ids, void* out_scores, hipStream_t s, bool timing) {
+int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int32_t qt, const ScoreOpts& so_in,
+                       int32_t* out_ids, void* out_scores, hipStream_t s, bool timing, int raise = -1) {
+    ScoreOpts so = so_in;
+    so.raise = raise >= 0 ? raise : (b->any_raise ? 1 : 0);
     Workspace ws;
     carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
     (void)hipGetLastError();  // launches below report their own status; drop any earlier, unrelated one
@@ -965,6 +995,16 @@ struct gs_graph_s {
     int device = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // the search as captured, for replays after an update that the captured kernels
+    // do not cover (a product that may round to 0 units): then it is enqueued directly
+    int raise = 1;
+    gs_index index = nullptr;
+    gs_batch batch = nullptr;
+    void* workspace = nullptr;
+    int32_t qt = 1;
+    ScoreOpts so{};
+    int32_t* out_ids = nullptr;
+    void* out_scores = nullptr;
     ~gs_graph_s() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1016,7 +1056,15 @@ int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspa
         delete gr;
         return fail(GS_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
-    rc = enqueue_search(ix, b, b->n_queries, workspace, qt, so, out_ids, out_scores, cs, false);
+    gr->raise = b->any_raise ? 1 : 0;
+    gr->index = ix;
+    gr->batch = b;
+    gr->workspace = workspace;
+    gr->qt = qt;
+    gr->so = so;
+    gr->out_ids = out_ids;
+    gr->out_scores = out_scores;
+    rc = enqueue_search(ix, b, b->n_queries, workspace, qt, so, out_ids, out_scores, cs, false, gr->raise);
     e = hipStreamEndCapture(cs, &gr->graph);
     (void)hipStreamDestroy(cs);
     if (rc != GS_OK) {
@@ -1101,6 +1149,9 @@ int32_t gs_graph_launch(gs_graph gr, void* hip_stream) {
     g_err.clear();
     if (!gr) return fail(GS_EINVAL, "graph is null");
     DeviceGuard g(gr->device);
+    if (gr->batch->any_raise && !gr->raise)
+        return enqueue_search(gr->index, gr->batch, gr->batch->n_queries, gr->workspace, gr->qt, gr->so, gr->out_ids,
+                              gr->out_scores, (hipStream_t)hip_stream, false, 1);
     GS_HIP(hipGraphLaunch(gr->exec, (hipStream_t)hip_stream));
     return GS_OK;
 }

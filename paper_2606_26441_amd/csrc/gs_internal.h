@@ -15,6 +15,10 @@ constexpr int kWave = 64;             // CDNA wavefront
 constexpr int kBlock = 64;            // postings per padded block (one wavefront)
 constexpr int kGrainShift = 13;       // segment-table doc-tile granularity: 8192 docs
 constexpr int kMaxQueryNnz = 256;     // GS_MAX_QUERY_NNZ
+constexpr int kMaxChunk = 1024;       // largest chunk of the doc-tiled kernels (postings)
+// post_lo and post_w carry kMaxChunk zeroed entries past the last posting, so a
+// chunk's full-width loads stay inside the arrays (lanes past its end are masked).
+constexpr size_t kPostSlack = kMaxChunk;
 constexpr int kMaxK = 4096;           // GS_MAX_K
 constexpr int kHistBits = 11;         // selection digit width (first digit fused into scoring)
 constexpr int kHistBins = 1 << kHistBits;
@@ -74,6 +78,7 @@ struct DevBatch {
     // integer number of units 2^-F(q) and summed exactly as an unsigned 64-bit integer; F(q) is
     // chosen per query so that every product of the query stays below 2^51 units.
     const double* q_fx;        // [q_nnz] w_q * 2^F(q) (exact)
+    const int32_t* q_bump;     // [q_nnz] 1 if a positive product of the term can round to 0 units
     const double* q_scale;     // [n] 2^-F(q)
     const double* q_abs_err;   // [n] bound on |fixed-point sum - exact sum|
     const int64_t* q_work;     // [n] postings of the query's terms (work estimate)
@@ -118,6 +123,7 @@ struct ScoreOpts {
     int tile_shift;   // doc tile of the TILED/SHARED kernels = 1 << tile_shift docs
     int chunk;        // postings per work item
     int group;
+    int raise = 1;    // fixed point: some positive product of the batch may round to 0 units
 };
 
 // Upload a query batch (gs_batch_update). With wait == false it returns once the

@@ -85,12 +85,26 @@ __device__ __forceinline__ T wave_sum(T v) {
 // [2^52, 2^53) where the fp64 spacing is 1 and its low bits are the product
 // rounded to the nearest integer. A positive product that rounds to 0 is raised
 // to 1, so a product is zero exactly when w_q * w_d is zero.
+// The same product without the raise, for batches in which every positive
+// product is at least one unit (decided per query term on the host).
+__device__ __forceinline__ unsigned long long fx_product_units(double qd, uint32_t wbits) {
+    constexpr double kTwo52 = 4503599627370496.0;
+    const double wd = (double)__uint_as_float(wbits);
+    return (unsigned long long)__double_as_longlong(__builtin_fma(qd, wd, kTwo52)) - 0x4330000000000000ull;
+}
+
 __device__ __forceinline__ unsigned long long fx_product(double qd, uint32_t wbits) {
     constexpr double kTwo52 = 4503599627370496.0;
     const double wd = (double)__uint_as_float(wbits);
     const unsigned long long r =
         (unsigned long long)__double_as_longlong(__builtin_fma(qd, wd, kTwo52)) - 0x4330000000000000ull;
     return r | (unsigned long long)((r == 0ull) & (wbits != 0u));  // qd > 0 for every processed term
+}
+
+template <bool RB>
+__device__ __forceinline__ unsigned long long fx_prod(double qd, uint32_t wbits) {
+    if constexpr (RB) return fx_product(qd, wbits);
+    else return fx_product_units(qd, wbits);
 }
 
 __device__ __forceinline__ uint32_t stored_bits(const void* p, int64_t i, std::integral_constant<int, kFP32>) {
@@ -199,7 +213,7 @@ __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* ta
 // Score one (query, doc tile) work item into LDS and flush it. Every thread of
 // the workgroup calls this; it ends after the flush (callers that loop must
 // synchronise before reusing the LDS).
-template <int P, int TS, int CH>
+template <int P, int TS, int CH, bool RB>
 __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& qb, int32_t q0, int64_t tile, int ql,
                                            uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
                                            uint32_t* lds, TileShared& sh) {
@@ -310,13 +324,13 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
             const double qd = sh.seg_qd[k.seg];
 #pragma unroll
             for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc64[k.doc[u] - lbase], fx_product(qd, k.w[u]));
+                if (lane + u * kWave < k.n) atomicAdd(&acc64[k.doc[u] - lbase], fx_prod<RB>(qd, k.w[u]));
         } else if constexpr (AF == kAccFx32) {
             // the query's scale keeps every doc's sum below 2^32 units
             const double qd = sh.seg_qd[k.seg];
 #pragma unroll
             for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - lbase], (uint32_t)fx_product(qd, k.w[u]));
+                if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - lbase], (uint32_t)fx_prod<RB>(qd, k.w[u]));
         } else {
             const uint32_t q8v = sh.seg_q8[k.seg];
 #pragma unroll
@@ -348,13 +362,13 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
 // workgroups, so each query streams its own postings from HBM.
 // Both scoring kernels are held to 128 VGPRs (four wavefronts per SIMD): two
 // 512-thread workgroups per CU, which is what their LDS footprint allows.
-template <int P, int TS, int CH>
+template <int P, int TS, int CH, bool RB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_tiled(
     DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
                                                      int64_t ld, uint32_t* __restrict__ hist1) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ TileShared sh;
-    score_tile<P, TS, CH>(ix, qb, q0, (int64_t)blockIdx.x, (int)blockIdx.y, S, ld, hist1, lds, sh);
+    score_tile<P, TS, CH, RB>(ix, qb, q0, (int64_t)blockIdx.x, (int)blockIdx.y, S, ld, hist1, lds, sh);
 }
 
 // Persistent form of the shared traversal: a grid of (resident workgroups,
@@ -363,7 +377,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 // of a tile are its queries in the order given by `order` (heaviest first), so
 // every query of a tile runs on one XCD while the tile's postings are in its L2.
 // Every workgroup leaves the loop once its XCD's counter passes the item count.
-template <int P, int TS, int CH>
+template <int P, int TS, int CH, bool RB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_persistent(
     DevIndex ix, DevBatch qb, int32_t q0, int32_t qt,
                                                           const int32_t* __restrict__ order,
@@ -383,7 +397,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (item >= items) break;
         const int64_t tile = x + 8 * (item / qt);
         const int ql = order[item % qt];
-        score_tile<P, TS, CH>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh);
+        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh);
         __syncthreads();
     }
 }
@@ -575,7 +589,7 @@ hipError_t by_precision(int p, F f) {
     return hipErrorInvalidValue;
 }
 
-template <int P, int TS, int CH>
+template <int P, int TS, int CH, bool RB>
 hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, bool persistent,
                             const Workspace& ws, int64_t ld, hipStream_t s) {
     const int64_t n_tiles = (ix.n_docs + (1 << TS) - 1) >> TS;
@@ -583,10 +597,10 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
     if (lds > 150 * 1024) return hipErrorInvalidValue;
     if (lds > 65536) {
         static const hipError_t attr = [&] {
-            hipError_t e = hipFuncSetAttribute((const void*)k_score_tiled<P, TS, CH>,
+            hipError_t e = hipFuncSetAttribute((const void*)k_score_tiled<P, TS, CH, RB>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e == hipSuccess)
-                e = hipFuncSetAttribute((const void*)k_score_persistent<P, TS, CH>,
+                e = hipFuncSetAttribute((const void*)k_score_persistent<P, TS, CH, RB>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             return e;
         }();
@@ -596,7 +610,7 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         }
     }
     if (!persistent) {
-        hipLaunchKernelGGL((k_score_tiled<P, TS, CH>), dim3((unsigned)n_tiles, (unsigned)qt), dim3(512), lds, s, ix,
+        hipLaunchKernelGGL((k_score_tiled<P, TS, CH, RB>), dim3((unsigned)n_tiles, (unsigned)qt), dim3(512), lds, s, ix,
                            qb, q0, ws.scores, ld, ws.hist1);
         GS_CHECK_LAUNCH("k_score_tiled");
         return hipSuccess;
@@ -606,7 +620,7 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         int dev = 0, per_cu = 0;
         hipDeviceProp_t p{};
         if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_score_persistent<P, TS, CH>, 512,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_score_persistent<P, TS, CH, RB>, 512,
                                                          lds) != hipSuccess)
             return 0;
         return std::max(8, (p.multiProcessorCount * std::max(per_cu, 1)) / 8 * 8);
@@ -614,21 +628,21 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
     if (grid <= 0) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_work_order, dim3((unsigned)((qt + 255) / 256)), dim3(256), 0, s, qb, q0, qt, ws.order);
     GS_CHECK_LAUNCH("k_work_order");
-    hipLaunchKernelGGL((k_score_persistent<P, TS, CH>), dim3((unsigned)grid), dim3(512), lds, s, ix, qb, q0, qt,
+    hipLaunchKernelGGL((k_score_persistent<P, TS, CH, RB>), dim3((unsigned)grid), dim3(512), lds, s, ix, qb, q0, qt,
                        (const int32_t*)ws.order, ws.counters, ws.scores, ld, ws.hist1);
     GS_CHECK_LAUNCH("k_score_persistent");
     return hipSuccess;
 }
 
-template <int P, int TS>
+template <int P, int TS, bool RB>
 hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, bool persistent,
                        const Workspace& ws, int64_t ld, hipStream_t s) {
     switch (chunk) {
-        case 64: return launch_tiled_one<P, TS, 64>(ix, qb, q0, qt, persistent, ws, ld, s);
-        case 128: return launch_tiled_one<P, TS, 128>(ix, qb, q0, qt, persistent, ws, ld, s);
-        case 256: return launch_tiled_one<P, TS, 256>(ix, qb, q0, qt, persistent, ws, ld, s);
-        case 512: return launch_tiled_one<P, TS, 512>(ix, qb, q0, qt, persistent, ws, ld, s);
-        case 1024: return launch_tiled_one<P, TS, 1024>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 64: return launch_tiled_one<P, TS, 64, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 128: return launch_tiled_one<P, TS, 128, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 256: return launch_tiled_one<P, TS, 256, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 512: return launch_tiled_one<P, TS, 512, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 1024: return launch_tiled_one<P, TS, 1024, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
     }
     return hipErrorInvalidValue;
 }
@@ -666,15 +680,21 @@ hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0
     return by_precision(ix.precision, [&](auto pc) -> hipError_t {
         constexpr int P = decltype(pc)::value;
         const bool persistent = o.kernel == 4;  // GS_KERNEL_SHARED: persistent, tile-major, XCD-aware
-        switch (o.tile_shift) {
-            case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
-            case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
-            case 15:
-                if constexpr (acc_form<P>() != kAccFx64)
-                    return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
-                return hipErrorInvalidValue;  // 32768 64-bit accumulators exceed one CU's LDS
-        }
-        return hipErrorInvalidValue;
+        auto go = [&](auto rb) -> hipError_t {
+            constexpr bool RB = decltype(rb)::value;
+            switch (o.tile_shift) {
+                case 13: return tiled_chunk<P, 13, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
+                case 14: return tiled_chunk<P, 14, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
+                case 15:
+                    if constexpr (acc_form<P>() != kAccFx64)
+                        return tiled_chunk<P, 15, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
+                    return hipErrorInvalidValue;  // 32768 64-bit accumulators exceed one CU's LDS
+            }
+            return hipErrorInvalidValue;
+        };
+        // fixed point: the raise of products that round to 0 units only where the batch needs it
+        if constexpr (P == kU8) return go(std::false_type());
+        else return o.raise ? go(std::true_type()) : go(std::false_type());
     });
 }
 

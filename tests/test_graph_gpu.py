@@ -83,3 +83,43 @@ def test_partial_update_pads_with_empty_queries(data):
     assert np.all(ids[4:] == -1) and np.all(sc[4:] == 0)
     with pytest.raises(gs.GsError):
         batch.update(q1, 100)  # 24 queries do not fit a capacity of 10
+
+
+def test_graph_replay_after_a_refill_that_needs_the_raise(data):
+    # fixed point: a positive product below one unit is raised to one unit; the kernels without
+    # that step serve batches in which no product can be that small. A graph captured on such a
+    # batch and replayed after a refill that needs the step must give the direct search's answer.
+    gs, torch = _gs()
+    docs, q1, q2 = data
+    q1_terms = set(q1.terms.tolist())
+    t_small = next(int(t) for t in q2.row(0)[0] if int(t) not in q1_terms)
+    w = docs.weights.copy()
+    hits = np.flatnonzero(docs.terms == t_small)[:50]
+    w[hits] = np.float32(1e-30)
+    docs_s = workload.SparseRows(docs.row_ptr, docs.terms, w, docs.vocab)
+    idx = gs.Index.from_rows(docs_s, "fp32")
+    opts = gs.make_opts("tiled")
+    k1 = np.full(q1.n_rows, 100, np.int32)
+    k2 = np.full(q2.n_rows, 100, np.int32)
+    direct = {}
+    for name, qs, kk in (("q1", q1, k1), ("q2", q2, k2)):
+        b = idx.batch(qs, kk, k_max=100)
+        ids, sc = idx.search(b, idx.workspace(qs.n_rows, opts), opts)
+        torch.cuda.synchronize()
+        direct[name] = (ids.cpu().numpy(), sc.cpu().numpy())
+        check_batch("fp32", docs_s, qs, direct[name][0], direct[name][1], kk, what="direct " + name)
+    batch = gs.Batch.reserve(idx, q1.n_rows, max(q1.nnz, q2.nnz), 100)
+    ws = idx.workspace(q1.n_rows, opts)
+    ids = torch.empty((q1.n_rows, 100), dtype=torch.int32, device="cuda")
+    sc = torch.empty((q1.n_rows, 100), dtype=torch.float32, device="cuda")
+    batch.update(q1, k1)
+    graph = gs.Graph(idx, batch, ws, ids, sc, opts)
+    for name in ["q1", "q2", "q1"]:
+        torch.cuda.synchronize()
+        batch.update(q1 if name == "q1" else q2, k1 if name == "q1" else k2)
+        ids.fill_(-7)
+        graph.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(ids.cpu().numpy(), direct[name][0]), name
+        assert np.array_equal(sc.cpu().numpy(), direct[name][1]), name
+    graph.close()
