@@ -64,6 +64,15 @@ template <> struct WF<kU8> {
     static __device__ __forceinline__ uint32_t bits(int v) { return (uint32_t)v; }
 };
 
+// A wave-uniform double moved into scalar registers: the predicated per-posting
+// blocks that use it then carry no wait on the LDS read that produced it.
+__device__ __forceinline__ double uniform_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(b >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ unsigned long long comp_key(uint32_t key, uint32_t id) {
     return ((unsigned long long)key << 32) | (unsigned long long)(~id);
 }
@@ -321,18 +330,18 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     };
     auto apply = [&](const Chunk& k) {
         if constexpr (AF == kAccFx64) {
-            const double qd = sh.seg_qd[k.seg];
+            const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
             for (int u = 0; u < U; u++)
                 if (lane + u * kWave < k.n) atomicAdd(&acc64[k.doc[u] - lbase], fx_prod<RB>(qd, k.w[u]));
         } else if constexpr (AF == kAccFx32) {
             // the query's scale keeps every doc's sum below 2^32 units
-            const double qd = sh.seg_qd[k.seg];
+            const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
             for (int u = 0; u < U; u++)
                 if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - lbase], (uint32_t)fx_prod<RB>(qd, k.w[u]));
         } else {
-            const uint32_t q8v = sh.seg_q8[k.seg];
+            const uint32_t q8v = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.seg_q8[k.seg]);
 #pragma unroll
             for (int u = 0; u < U; u++)
                 if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - lbase], q8v * k.w[u]);
