@@ -197,10 +197,11 @@ struct TileShared {
 // segment index, first posting and length, kept in scalar registers. The
 // segment comes from the chunk table when the tile has one, else from a binary
 // search over the chunk prefix.
+template <bool TAB>
 __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* tab, int nq, int c, int ch, int* seg,
                                          int64_t* p0, int* n) {
     int lo;
-    if (tab) {
+    if constexpr (TAB) {
         lo = tab[c];
     } else {
         lo = 0;
@@ -234,7 +235,8 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     uint32_t* acc32 = lds;                                                   // [TILE] (bf16, uint8)
     uint32_t* hist = lds + TILE * AW;                                        // [kHistBins]
 
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: chunk bookkeeping stays scalar
     const int q = q0 + ql;
     if (qb.k[q] == 0) return;  // nothing is selected for it (also every padding slot of a batch)
     const int64_t N = ix.n_docs;
@@ -307,58 +309,74 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         __syncthreads();
     }
     struct Chunk {
-        int doc[U];
-        uint32_t w[U];
+        uint32_t doc[U];  // doc id modulo 65536
+        uint32_t w[U];    // stored weight as fp32 bits, or the uint8 impact
         int seg, n;
     };
+    using WT = std::conditional_t<P == kU8, uint8_t, std::conditional_t<P == kBF16, uint16_t, uint32_t>>;
     // Loads are straight-line (no branch around them, so the compiler can wait for
     // the older chunk only): lanes past the end of a chunk re-read its last posting,
-    // and an empty slot reads posting 0 (the arrays are never empty).
-    auto load = [&](int c, Chunk& k, bool valid) {
+    // and an empty slot reads posting 0 (the arrays are never empty). The chunk's
+    // base is wave-uniform (scalar registers) and each lane's offset a clamped
+    // 32-bit value, so no 64-bit address arithmetic is done per posting. The
+    // chunk lookup is branch-free with the chunk table (an invalid slot looks up
+    // chunk 0 and gets length 0).
+    auto load = [&](auto use_tab, int c, Chunk& k, bool valid) {
         int64_t p0 = 0;
-        k.seg = 0;
-        k.n = 0;
-        if (valid) chunk_at(sh, tab, nq, c, CH, &k.seg, &p0, &k.n);
-        const int last = max(k.n - 1, 0);
+        int n = 0;
+        chunk_at<decltype(use_tab)::value>(sh, tab, nq, valid ? c : 0, CH, &k.seg, &p0, &n);
+        k.n = valid ? n : 0;
+        const uint32_t last = (uint32_t)max(k.n - 1, 0);
+        const char* lb = reinterpret_cast<const char*>(ix.post_lo + p0);
+        const char* wb = reinterpret_cast<const char*>(reinterpret_cast<const WT*>(ix.post_w) + p0);
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int64_t p = p0 + min(lane + u * kWave, last);
-            k.doc[u] = ix.post_lo[p];
-            if constexpr (P == kU8) k.w[u] = ((const uint8_t*)ix.post_w)[p];
-            else k.w[u] = stored_bits(ix.post_w, p, std::integral_constant<int, P>());
+            const uint32_t off = min((uint32_t)(lane + u * kWave), last);
+            k.doc[u] = *reinterpret_cast<const uint16_t*>(lb + off * 2u);
+            const uint32_t wv = *reinterpret_cast<const WT*>(wb + off * (uint32_t)sizeof(WT));
+            k.w[u] = P == kBF16 ? wv << 16 : wv;
         }
     };
+    // accumulators indexed by doc id modulo 65536 (the tile's offset folded into the base)
+    unsigned long long* acc64f = acc64 - lbase;
+    uint32_t* acc32f = acc32 - lbase;
     auto apply = [&](const Chunk& k) {
         if constexpr (AF == kAccFx64) {
             const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
             for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc64[k.doc[u] - lbase], fx_prod<RB>(qd, k.w[u]));
+                if (lane + u * kWave < k.n) atomicAdd(&acc64f[k.doc[u]], fx_prod<RB>(qd, k.w[u]));
         } else if constexpr (AF == kAccFx32) {
             // the query's scale keeps every doc's sum below 2^32 units
             const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
             for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - lbase], (uint32_t)fx_prod<RB>(qd, k.w[u]));
+                if (lane + u * kWave < k.n) atomicAdd(&acc32f[k.doc[u]], (uint32_t)fx_prod<RB>(qd, k.w[u]));
         } else {
             const uint32_t q8v = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.seg_q8[k.seg]);
 #pragma unroll
             for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc32[k.doc[u] - lbase], q8v * k.w[u]);
+                if (lane + u * kWave < k.n) atomicAdd(&acc32f[k.doc[u]], q8v * k.w[u]);
         }
     };
-    Chunk A, B;
-    int c = wave;
-    load(c, A, c < total);
-    while (c < total) {
-        const int cb = c + NW;
-        load(cb, B, cb < total);
-        apply(A);
-        if (cb >= total) break;
-        const int ca = cb + NW;
-        load(ca, A, ca < total);
-        apply(B);
-        c = ca;
+    auto run = [&](auto use_tab) {
+        Chunk A, B;
+        int c = wave;
+        load(use_tab, c, A, c < total);
+        while (c < total) {
+            const int cb = c + NW;
+            load(use_tab, cb, B, cb < total);
+            apply(A);
+            if (cb >= total) break;
+            const int ca = cb + NW;
+            load(use_tab, ca, A, ca < total);
+            apply(B);
+            c = ca;
+        }
+    };
+    if (total > 0) {
+        if (tab) run(std::true_type());
+        else run(std::false_type());
     }
     __syncthreads();
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
