@@ -340,24 +340,32 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // accumulators indexed by doc id modulo 65536 (the tile's offset folded into the base)
     unsigned long long* acc64f = acc64 - lbase;
     uint32_t* acc32f = acc32 - lbase;
+    // A full chunk (every lane holds a posting in every slot) adds without the
+    // per-posting predicate; the last chunk of a segment is predicated.
     auto apply = [&](const Chunk& k) {
-        if constexpr (AF == kAccFx64) {
-            const double qd = uniform_f64(sh.seg_qd[k.seg]);
+        auto add = [&](auto pred) {
+            constexpr bool PRED = decltype(pred)::value;
+            if constexpr (AF == kAccFx64) {
+                const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
-            for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc64f[k.doc[u]], fx_prod<RB>(qd, k.w[u]));
-        } else if constexpr (AF == kAccFx32) {
-            // the query's scale keeps every doc's sum below 2^32 units
-            const double qd = uniform_f64(sh.seg_qd[k.seg]);
+                for (int u = 0; u < U; u++)
+                    if (!PRED || lane + u * kWave < k.n) atomicAdd(&acc64f[k.doc[u]], fx_prod<RB>(qd, k.w[u]));
+            } else if constexpr (AF == kAccFx32) {
+                // the query's scale keeps every doc's sum below 2^32 units
+                const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
-            for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc32f[k.doc[u]], (uint32_t)fx_prod<RB>(qd, k.w[u]));
-        } else {
-            const uint32_t q8v = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.seg_q8[k.seg]);
+                for (int u = 0; u < U; u++)
+                    if (!PRED || lane + u * kWave < k.n)
+                        atomicAdd(&acc32f[k.doc[u]], (uint32_t)fx_prod<RB>(qd, k.w[u]));
+            } else {
+                const uint32_t q8v = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.seg_q8[k.seg]);
 #pragma unroll
-            for (int u = 0; u < U; u++)
-                if (lane + u * kWave < k.n) atomicAdd(&acc32f[k.doc[u]], q8v * k.w[u]);
-        }
+                for (int u = 0; u < U; u++)
+                    if (!PRED || lane + u * kWave < k.n) atomicAdd(&acc32f[k.doc[u]], q8v * k.w[u]);
+            }
+        };
+        if (k.n == CH) add(std::false_type());
+        else add(std::true_type());
     };
     auto run = [&](auto use_tab) {
         Chunk A, B;
