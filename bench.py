@@ -56,11 +56,12 @@ def parse():
     ap.add_argument("--batched", default="u8,bf16",
                     help="precisions for the 4,096-query uneven batch (autotuned, graph vs plain), or 'none'")
     ap.add_argument("--batched-queries", type=int, default=4096)
-    ap.add_argument("--serving", default="200,800,2000,12000", help="Poisson arrival rates (QPS) for the serving loop, or 'none'")
+    ap.add_argument("--serving", default="200,800,2000,12000,16000", help="Poisson arrival rates (QPS) for the serving loop, or 'none'")
     ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--serving-precision", default="u8")
-    ap.add_argument("--serving-batch", type=int, default=32, help="most queries per device step of the server")
+    ap.add_argument("--serving-batch", type=int, default=64, help="most queries per device step of the server")
     ap.add_argument("--serving-slots", type=int, default=4, help="device slots (concurrent steps) of the server")
+    ap.add_argument("--serving-kernel", default="shared", choices=["tiled", "shared"], help="scoring kernel of the server")
     return ap.parse_args()
 
 
@@ -295,8 +296,9 @@ def run_serving(gs, torch, docs, args):
     pool = workload.queries_lognormal(8192, seed=91)
     ks = workload.k_mix(8192, seed=92)
     max_batch, n_slots = args.serving_batch, args.serving_slots
-    srv = gs.Server(idx, max_batch=max_batch, n_slots=n_slots, k_max=1000, opts=gs.make_opts("tiled"))
-    res = {"precision": prec, "max_batch": max_batch, "n_slots": n_slots, "slot_bytes": srv.stats()["slot_bytes"],
+    srv = gs.Server(idx, max_batch=max_batch, n_slots=n_slots, k_max=1000, opts=gs.make_opts(args.serving_kernel))
+    res = {"precision": prec, "kernel": args.serving_kernel, "max_batch": max_batch, "n_slots": n_slots,
+           "slot_bytes": srv.stats()["slot_bytes"],
            "query_law": "lognormal median 25, sigma 0.8, [5, 250]; k over {10, 100, 1000}"}
     for q in range(64):  # warm-up
         t, w = pool.row(q)

@@ -26,12 +26,13 @@ def data():
     return docs, qs, k
 
 
+@pytest.mark.parametrize("kernel", ["tiled", "shared"])
 @pytest.mark.parametrize("precision", ["u8", "fp32"])
-def test_results_alone_equal_results_in_the_mix(data, precision):
+def test_results_alone_equal_results_in_the_mix(data, precision, kernel):
     gs, _ = _gs()
     docs, qs, k = data
     idx = gs.Index.from_rows(docs, precision)
-    srv = gs.Server(idx, max_batch=8, n_slots=3, k_max=1000)
+    srv = gs.Server(idx, max_batch=8, n_slots=3, k_max=1000, opts=gs.make_opts(kernel))
     # alone: one request at a time
     alone = []
     for q in range(12):
