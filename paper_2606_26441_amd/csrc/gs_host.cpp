@@ -885,9 +885,12 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
     so->tile_shift = ix->precision == kFP32 ? 13 : 14;
     so->chunk = 1024;  // measured fastest for both doc-tiled forms at every tile size
     so->group = 4;
+    so->seed_stride = 1;  // fused filtering wanted (the stride itself is chosen per search)
     if (!o) return GS_OK;
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < 2; i++)
         if (o->reserved[i] != 0) return fail(GS_EINVAL, "reserved option fields must be 0");
+    if (o->no_fused_filter != 0 && o->no_fused_filter != 1) return fail(GS_EINVAL, "no_fused_filter must be 0 or 1");
+    if (o->no_fused_filter) so->seed_stride = 0;
     if (o->kernel < GS_KERNEL_AUTO || o->kernel > GS_KERNEL_SHARED) return fail(GS_EINVAL, "unknown kernel");
     if (o->kernel != GS_KERNEL_AUTO) so->kernel = o->kernel;
     if (so->kernel == GS_KERNEL_DOCPAR && !(ix->flags & GS_KEEP_FORWARD))
@@ -955,6 +958,18 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int
                        int32_t* out_ids, void* out_scores, hipStream_t s, bool timing, int raise = -1) {
     ScoreOpts so = so_in;
     so.raise = raise >= 0 ? raise : (b->any_raise ? 1 : 0);
+    // Fused candidate filtering (doc-tiled kernels): every stride-th tile seeds a lower bound
+    // of the k-th composite; the other tiles append their candidates while they are scored.
+    // The seed tiles should hold several times k documents: stride 8 up to k = 1024, 4 up to
+    // 2048, else off; it needs at least two seed tiles. It adds five launches to a search,
+    // which a few queries' row scans do not repay: searches of fewer than 32 queries scan.
+    {
+        const bool tiled = so.kernel == GS_KERNEL_TILED || so.kernel == GS_KERNEL_SHARED;
+        const int64_t n_tiles = (ix->n_docs + (1ll << so.tile_shift) - 1) >> so.tile_shift;
+        int stride = b->k_max <= 1024 ? 8 : (b->k_max <= 2048 ? 4 : 0);
+        if (!tiled || so.seed_stride == 0 || n_tiles < 2 * (int64_t)stride || nq < 32) stride = 0;
+        so.seed_stride = stride;
+    }
     Workspace ws;
     carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
     (void)hipGetLastError();  // launches below report their own status; drop any earlier, unrelated one
@@ -966,12 +981,18 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int
             SpanRecorder rec(timing ? 0 : -1, s);
             if (so.kernel == GS_KERNEL_ATOMIC) e = launch_score_atomic(ix->dev, b->dev, q0, n, so, ws, s);
             else if (so.kernel == GS_KERNEL_DOCPAR) e = launch_score_docpar(ix->dev, b->dev, q0, n, so, ws, s);
-            else e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s);
+            else if (so.seed_stride == 0) e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s);
+            else {
+                e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 1);  // seed tiles
+                if (e == hipSuccess) e = launch_seed_bound(ix->dev, b->dev, q0, n, ws, s, so.tile_shift, so.seed_stride);
+                if (e == hipSuccess) e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 2);  // the rest
+            }
             rec.end(s);
         }
         if (e == hipSuccess) {
             SpanRecorder rec(timing ? 1 : -1, s);
-            e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s);
+            e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s, so.tile_shift,
+                              so.seed_stride);
             rec.end(s);
         }
         if (e != hipSuccess)

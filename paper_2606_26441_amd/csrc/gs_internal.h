@@ -23,6 +23,7 @@ constexpr int kMaxK = 4096;           // GS_MAX_K
 constexpr int kHistBits = 11;         // selection digit width (first digit fused into scoring)
 constexpr int kHistBins = 1 << kHistBits;
 constexpr int kCandCap = 32768;       // candidates kept per query by the filter pass
+constexpr int kFusedCap = 24576;      // of which appended while scoring (fused filtering)
 constexpr int kRefinePasses = 6;      // enough to resolve any 64-bit composite key
 constexpr int kFirstShiftFloat = 52;  // first digit of a float key: bits 30..20
 
@@ -97,6 +98,11 @@ struct SelState {
     int32_t overflow;           // candidate or band buffer overflow
     int32_t need_band_pass;     // bf16: band reaches below the filter threshold
     double tau;                 // bf16: band threshold on approximate scores
+    // fused candidate filtering: a lower bound of the k-th composite from the seed tiles;
+    // the other tiles append every composite >= bound while they are scored
+    unsigned long long bound;
+    int32_t fused;              // 1 while the appended candidates stand in for the row scan
+    int32_t fused_over;         // the appends passed kFusedCap
 };
 
 // Workspace carve-up for a tile of qt queries.
@@ -124,7 +130,21 @@ struct ScoreOpts {
     int chunk;        // postings per work item
     int group;
     int raise = 1;    // fixed point: some positive product of the batch may round to 0 units
+    int seed_stride = 0;  // fused candidate filtering: every seed_stride-th doc tile seeds the bound (0: off)
 };
+
+// Doc tiles of a scoring launch: phase 0 all tiles, phase 1 the seed tiles
+// (multiples of stride), phase 2 the others. v is the launch's tile index.
+__host__ __device__ inline int64_t phase_tiles(int phase, int stride, int64_t n_tiles) {
+    if (phase == 0) return n_tiles;
+    const int64_t seeds = (n_tiles + stride - 1) / stride;
+    return phase == 1 ? seeds : n_tiles - seeds;
+}
+__host__ __device__ inline int64_t phase_tile(int phase, int stride, int64_t v) {
+    if (phase == 0) return v;
+    if (phase == 1) return v * stride;
+    return (v / (stride - 1)) * stride + v % (stride - 1) + 1;
+}
 
 // Upload a query batch (gs_batch_update). With wait == false it returns once the
 // copies are enqueued on hip_stream (staged in pinned memory), for callers that
@@ -136,7 +156,7 @@ int32_t batch_update(struct ::gs_batch_s* b, const int64_t* q_row_ptr, int32_t n
 // ---- launchers (gs_score.hip) ----
 hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s);
 hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
-                              const ScoreOpts& o, const Workspace& ws, hipStream_t s);
+                              const ScoreOpts& o, const Workspace& ws, hipStream_t s, int phase = 0);
 hipError_t launch_score_atomic(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                                const ScoreOpts& o, const Workspace& ws, hipStream_t s);
 hipError_t launch_score_docpar(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
@@ -149,6 +169,9 @@ hipError_t launch_fill(void* p, int64_t n_words, uint32_t v, hipStream_t s);  //
 // ---- launchers (gs_topk.hip) ----
 hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                          const Workspace& ws, int32_t* out_ids, void* out_scores, int32_t* diag,
-                         hipStream_t s);
+                         hipStream_t s, int tile_shift = 0, int seed_stride = 0);
+// fused filtering: the bound of every query of the tile from its seed-tile histogram
+hipError_t launch_seed_bound(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
+                             const Workspace& ws, hipStream_t s, int tile_shift, int stride);
 
 }  // namespace gs

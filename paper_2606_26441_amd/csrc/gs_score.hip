@@ -129,9 +129,28 @@ __device__ __forceinline__ uint32_t stored_bits(const void* p, int64_t i, std::i
 // kAccFx64 (unsigned fixed point in units of `scale`, written as fp32 bits).
 enum AccForm { kAccInt = 0, kAccFx32 = 1, kAccFx64 = 2 };
 
+// Fused candidate filtering: append the composites c >= bound of the lanes that
+// take one to the query's candidate buffer (one atomic per wavefront; hits are
+// rare once the bound is set). Past kFusedCap the query is flagged instead.
+__device__ __forceinline__ void append_candidates(bool take, unsigned long long c, SelState* st,
+                                                  unsigned long long* C) {
+    const unsigned long long m = __ballot(take);
+    if (m == 0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int leader = __ffsll((long long)__ballot(1)) - 1;
+    int slot = 0;
+    if (lane == leader) {
+        slot = atomicAdd(&st->n_cand, __popcll(m));
+        if (slot + __popcll(m) > kFusedCap) st->fused_over = 1;
+    }
+    slot = __shfl(slot, leader, kWave) + __popcll(m & ((1ull << lane) - 1ull));
+    if (take && slot < kFusedCap) C[slot] = c;
+}
+
 template <int BS, int AF>
 __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, int tile_n, int64_t base, uint32_t* Sq,
-                                           int fs, double scale, uint32_t* hist_out) {
+                                           int fs, double scale, uint32_t* hist_out, bool append,
+                                           unsigned long long bound, SelState* st, unsigned long long* C) {
     const int tid = threadIdx.x;
     const int n4 = tile_n >> 2;
     for (int i = tid; i < n4; i += BS) {
@@ -151,7 +170,11 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
         reinterpret_cast<uint4*>(Sq)[i] = make_uint4(v[0], v[1], v[2], v[3]);
         const uint32_t d0 = (uint32_t)(base + 4 * i);
 #pragma unroll
-        for (int j = 0; j < 4; j++) atomicAdd(&hist[(comp_key(v[j], d0 + j) >> fs) & (kHistBins - 1)], 1u);
+        for (int j = 0; j < 4; j++) {
+            const unsigned long long c = comp_key(v[j], d0 + j);
+            atomicAdd(&hist[(c >> fs) & (kHistBins - 1)], 1u);
+            if (append) append_candidates(c >= bound, c, st, C);
+        }
     }
     for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
         uint32_t v;
@@ -159,7 +182,9 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
         else if constexpr (AF == kAccFx32) v = __float_as_uint((float)((double)((const uint32_t*)acc_v)[i] * scale));
         else v = ((const uint32_t*)acc_v)[i];
         Sq[i] = v;
-        atomicAdd(&hist[(comp_key(v, (uint32_t)(base + i)) >> fs) & (kHistBins - 1)], 1u);
+        const unsigned long long c = comp_key(v, (uint32_t)(base + i));
+        atomicAdd(&hist[(c >> fs) & (kHistBins - 1)], 1u);
+        if (append) append_candidates(c >= bound, c, st, C);
     }
     __syncthreads();
     for (int b = tid; b < kHistBins; b += BS)
@@ -226,7 +251,8 @@ __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* ta
 template <int P, int TS, int CH, bool RB>
 __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& qb, int32_t q0, int64_t tile, int ql,
                                            uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
-                                           uint32_t* lds, TileShared& sh) {
+                                           uint32_t* lds, TileShared& sh, bool append, SelState* state,
+                                           unsigned long long* cand) {
     constexpr int BS = 512, NW = BS / kWave, TILE = 1 << TS, U = CH / kWave, GPT = TS - kGrainShift;
     constexpr bool FX = P != kU8;                  // fixed-point products (fp32, bf16)
     constexpr int AF = acc_form<P>();
@@ -389,8 +415,12 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     __syncthreads();
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
     __syncthreads();
+    // fused filtering (the non-seed tiles of a query whose seed bound is set): append while flushing
+    SelState* st = state + ql;
+    const bool app = append && st->fused == 1 && !st->fused_over;  // no appends once past the cap
     flush_tile<BS, AF>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
-                       FX ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins);
+                       FX ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins, app, app ? st->bound : 0ull, st,
+                       cand + (int64_t)ql * kCandCap);
 }
 
 // Per-query form: grid (tiles, queries), the tiles of one query are consecutive
@@ -399,11 +429,12 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
 // 512-thread workgroups per CU, which is what their LDS footprint allows.
 template <int P, int TS, int CH, bool RB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_tiled(
-    DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S,
-                                                     int64_t ld, uint32_t* __restrict__ hist1) {
+    DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
+    int phase, int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ TileShared sh;
-    score_tile<P, TS, CH, RB>(ix, qb, q0, (int64_t)blockIdx.x, (int)blockIdx.y, S, ld, hist1, lds, sh);
+    score_tile<P, TS, CH, RB>(ix, qb, q0, phase_tile(phase, stride, (int64_t)blockIdx.x), (int)blockIdx.y, S, ld,
+                              hist1, lds, sh, phase == 2, state, cand);
 }
 
 // Persistent form of the shared traversal: a grid of (resident workgroups,
@@ -414,15 +445,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 // Every workgroup leaves the loop once its XCD's counter passes the item count.
 template <int P, int TS, int CH, bool RB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_persistent(
-    DevIndex ix, DevBatch qb, int32_t q0, int32_t qt,
-                                                          const int32_t* __restrict__ order,
-                                                          uint32_t* __restrict__ counters, uint32_t* __restrict__ S,
-                                                          int64_t ld, uint32_t* __restrict__ hist1) {
+    DevIndex ix, DevBatch qb, int32_t q0, int32_t qt, const int32_t* __restrict__ order,
+    uint32_t* __restrict__ counters, uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1, int phase,
+    int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ TileShared sh;
     __shared__ int64_t item_sh;
     const int x = (int)(blockIdx.x & 7);
-    const int64_t n_tiles = (ix.n_docs + (1 << TS) - 1) >> TS;
+    const int64_t n_tiles = phase_tiles(phase, stride, (ix.n_docs + (1 << TS) - 1) >> TS);
     const int64_t tiles_x = n_tiles > x ? (n_tiles - x + 7) / 8 : 0;
     const int64_t items = tiles_x * qt;
     for (;;) {
@@ -430,9 +460,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         __syncthreads();
         const int64_t item = item_sh;
         if (item >= items) break;
-        const int64_t tile = x + 8 * (item / qt);
+        const int64_t tile = phase_tile(phase, stride, x + 8 * (item / qt));
         const int ql = order[item % qt];
-        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh);
+        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh, phase == 2, state, cand);
         __syncthreads();
     }
 }
@@ -626,8 +656,9 @@ hipError_t by_precision(int p, F f) {
 
 template <int P, int TS, int CH, bool RB>
 hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, bool persistent,
-                            const Workspace& ws, int64_t ld, hipStream_t s) {
-    const int64_t n_tiles = (ix.n_docs + (1 << TS) - 1) >> TS;
+                            const Workspace& ws, int64_t ld, hipStream_t s, int phase, int stride) {
+    const int64_t n_tiles = phase_tiles(phase, stride, (ix.n_docs + (1 << TS) - 1) >> TS);
+    if (n_tiles <= 0) return hipSuccess;
     const size_t lds = (size_t)((1 << TS) * (acc_form<P>() == kAccFx64 ? 2 : 1) + kHistBins) * 4;
     if (lds > 150 * 1024) return hipErrorInvalidValue;
     if (lds > 65536) {
@@ -646,7 +677,7 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
     }
     if (!persistent) {
         hipLaunchKernelGGL((k_score_tiled<P, TS, CH, RB>), dim3((unsigned)n_tiles, (unsigned)qt), dim3(512), lds, s, ix,
-                           qb, q0, ws.scores, ld, ws.hist1);
+                           qb, q0, ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand);
         GS_CHECK_LAUNCH("k_score_tiled");
         return hipSuccess;
     }
@@ -661,23 +692,29 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         return std::max(8, (p.multiProcessorCount * std::max(per_cu, 1)) / 8 * 8);
     }();
     if (grid <= 0) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_work_order, dim3((unsigned)((qt + 255) / 256)), dim3(256), 0, s, qb, q0, qt, ws.order);
-    GS_CHECK_LAUNCH("k_work_order");
+    if (phase != 2) {  // the second launch of a fused search keeps the first one's order
+        hipLaunchKernelGGL(k_work_order, dim3((unsigned)((qt + 255) / 256)), dim3(256), 0, s, qb, q0, qt, ws.order);
+        GS_CHECK_LAUNCH("k_work_order");
+    } else {
+        const hipError_t e = launch_fill(ws.counters, 8, 0u, s);  // the first launch used the counters
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_score_persistent<P, TS, CH, RB>), dim3((unsigned)grid), dim3(512), lds, s, ix, qb, q0, qt,
-                       (const int32_t*)ws.order, ws.counters, ws.scores, ld, ws.hist1);
+                       (const int32_t*)ws.order, ws.counters, ws.scores, ld, ws.hist1, phase, stride, ws.state,
+                       ws.cand);
     GS_CHECK_LAUNCH("k_score_persistent");
     return hipSuccess;
 }
 
 template <int P, int TS, bool RB>
 hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, bool persistent,
-                       const Workspace& ws, int64_t ld, hipStream_t s) {
+                       const Workspace& ws, int64_t ld, hipStream_t s, int phase, int stride) {
     switch (chunk) {
-        case 64: return launch_tiled_one<P, TS, 64, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
-        case 128: return launch_tiled_one<P, TS, 128, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
-        case 256: return launch_tiled_one<P, TS, 256, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
-        case 512: return launch_tiled_one<P, TS, 512, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
-        case 1024: return launch_tiled_one<P, TS, 1024, RB>(ix, qb, q0, qt, persistent, ws, ld, s);
+        case 64: return launch_tiled_one<P, TS, 64, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 128: return launch_tiled_one<P, TS, 128, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 256: return launch_tiled_one<P, TS, 256, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 512: return launch_tiled_one<P, TS, 512, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 1024: return launch_tiled_one<P, TS, 1024, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
     }
     return hipErrorInvalidValue;
 }
@@ -710,7 +747,8 @@ hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s) {
 }
 
 hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const ScoreOpts& o,
-                              const Workspace& ws, hipStream_t s) {
+                              const Workspace& ws, hipStream_t s, int phase) {
+    const int stride = phase == 0 ? 1 : o.seed_stride;
     const int64_t ld = score_ld(ix.n_docs);
     return by_precision(ix.precision, [&](auto pc) -> hipError_t {
         constexpr int P = decltype(pc)::value;
@@ -718,11 +756,11 @@ hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0
         auto go = [&](auto rb) -> hipError_t {
             constexpr bool RB = decltype(rb)::value;
             switch (o.tile_shift) {
-                case 13: return tiled_chunk<P, 13, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
-                case 14: return tiled_chunk<P, 14, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
+                case 13: return tiled_chunk<P, 13, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
+                case 14: return tiled_chunk<P, 14, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
                 case 15:
                     if constexpr (acc_form<P>() != kAccFx64)
-                        return tiled_chunk<P, 15, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s);
+                        return tiled_chunk<P, 15, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
                     return hipErrorInvalidValue;  // 32768 64-bit accumulators exceed one CU's LDS
             }
             return hipErrorInvalidValue;

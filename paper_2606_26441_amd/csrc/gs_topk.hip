@@ -90,19 +90,104 @@ __global__ __launch_bounds__(64) void k_select_first(DevBatch qb, int32_t q0, in
     if (threadIdx.x != 0) return;
     const int fs = qb.first_shift[q];
     const int64_t ge = (int64_t)above + h[d];
+    int64_t kept;  // composites at or above the filter threshold
     if (precision == kBF16 && d > 0 && ge + h[d - 1] <= kCandCap) {
         // one bin lower: the bf16 error band below the k-th score then lies inside the candidates
         st->resolved = 1;
         st->lo = (unsigned long long)(d - 1) << fs;
+        kept = ge + h[d - 1];
     } else if (ge <= kCandCap) {
         st->resolved = 1;
         st->lo = (unsigned long long)d << fs;
+        kept = ge;
     } else {
         st->resolved = 0;
         st->prefix = (unsigned long long)d << fs;
         st->shift = fs;
         st->k_rem = (int32_t)(kq - above);
+        kept = 0;
     }
+    // Fused filtering holds the appended candidates (every composite >= the seed bound
+    // of the non-seed tiles; the bound is at most the threshold) and the filter then
+    // scans the seed tiles only. Otherwise the appended ones are dropped and the whole
+    // row is scanned: no bound, too many appended, or a refinement is needed.
+    if (st->fused == 1 && (st->resolved != 1 || st->fused_over || (int64_t)st->n_cand + kept > kCandCap)) {
+        st->fused = 0;
+        st->n_cand = 0;
+    }
+}
+
+// Fused filtering, after the seed tiles are scored. The bound of a query is the
+// lower edge of a two-digit bucket (22 bits of the composite key) that holds the
+// k-th largest composite among the seed tiles' documents: k_seed_bound finds the
+// first-digit bin from the histogram the seed tiles built, k_seed_hist counts the
+// next digit within that bin over the seed tiles' scores, and k_seed_refine picks
+// the sub-bin. The k-th largest over all documents is at least as large, so the
+// bound never exceeds it. With fewer than k seed documents there is no bound.
+__global__ __launch_bounds__(64) void k_seed_bound(DevBatch qb, int32_t q0, int64_t N,
+                                                   const uint32_t* __restrict__ hist1, SelState* __restrict__ state) {
+    const int ql = blockIdx.x, q = q0 + ql;
+    SelState* st = state + ql;
+    const int64_t kq = kq_of(qb, q, N);
+    if (kq == 0) {
+        if (threadIdx.x == 0) st->fused = 0;
+        return;
+    }
+    const uint32_t* h = hist1 + (int64_t)ql * kHistBins;
+    uint32_t above;
+    const int d = hist_walk(h, (uint32_t)kq, &above);
+    if (threadIdx.x != 0) return;
+    if ((int64_t)above + h[d] < kq) {
+        st->fused = 0;
+        return;
+    }
+    const int fs = qb.first_shift[q];
+    st->prefix = (unsigned long long)d << fs;
+    st->shift = fs;
+    st->k_rem = (int32_t)(kq - above);
+    st->fused = 2;  // refining
+}
+
+__global__ __launch_bounds__(512) void k_seed_hist(int64_t N, const uint32_t* __restrict__ S, int64_t ld,
+                                                   int tile_shift, int stride, const SelState* __restrict__ state,
+                                                   uint32_t* __restrict__ hist_ref) {
+    __shared__ uint32_t hist[kHistBins];
+    const int ql = blockIdx.y;
+    const SelState st = state[ql];
+    if (st.fused != 2) return;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kHistBins; i += 512) hist[i] = 0u;
+    __syncthreads();
+    const int shift = st.shift, nshift = max(shift - kHistBits, 0);
+    const unsigned long long want = st.prefix >> shift;
+    const unsigned long long mask = (1ull << (shift - nshift)) - 1ull;
+    const int64_t d0 = ((int64_t)blockIdx.x * stride) << tile_shift, d1 = min(N, d0 + (1ll << tile_shift));
+    const uint32_t* Sq = S + (int64_t)ql * ld;
+    for (int64_t d = d0 + tid; d < d1; d += 512) {
+        const unsigned long long c = comp_key(Sq[d], (uint32_t)d);
+        if ((c >> shift) == want) atomicAdd(&hist[(c >> nshift) & mask], 1u);
+    }
+    __syncthreads();
+    for (int b = tid; b < kHistBins; b += 512)
+        if (hist[b]) atomicAdd(&hist_ref[(int64_t)ql * kHistBins + b], hist[b]);
+}
+
+__global__ __launch_bounds__(64) void k_seed_refine(uint32_t* __restrict__ hist_ref, SelState* __restrict__ state) {
+    const int ql = blockIdx.x;
+    SelState* st = state + ql;
+    if (st->fused != 2) return;
+    uint32_t* h = hist_ref + (int64_t)ql * kHistBins;
+    uint32_t above;
+    const int e = hist_walk(h, (uint32_t)st->k_rem, &above);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHistBins; i += 64) h[i] = 0u;  // the refinement passes reuse the rows
+    if (threadIdx.x != 0) return;
+    const int nshift = max(st->shift - kHistBits, 0);
+    st->bound = st->prefix | ((unsigned long long)e << nshift);
+    st->prefix = 0;
+    st->shift = 0;
+    st->k_rem = 0;
+    st->fused = 1;
 }
 
 __global__ __launch_bounds__(512) void k_refine_hist(int32_t q0, int64_t N, const uint32_t* __restrict__ S, int64_t ld,
@@ -180,7 +265,8 @@ __device__ __forceinline__ void append_global(SelState* st, unsigned long long* 
 
 __global__ __launch_bounds__(512) void k_filter(int32_t q0, int64_t N, const uint32_t* __restrict__ S, int64_t ld,
                                                 int per_block, SelState* __restrict__ state,
-                                                unsigned long long* __restrict__ cand) {
+                                                unsigned long long* __restrict__ cand, int tile_shift,
+                                                int seed_stride) {
     __shared__ unsigned long long stage[kFilterStage];
     __shared__ int n_stage, g_base;
     const int ql = blockIdx.y;
@@ -190,26 +276,36 @@ __global__ __launch_bounds__(512) void k_filter(int32_t q0, int64_t N, const uin
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     if (tid == 0) n_stage = 0;
     __syncthreads();
-    const int64_t d0 = (int64_t)blockIdx.x * per_block, d1 = min(N, d0 + per_block);  // per_block % 256 == 0
+    const int64_t b0 = (int64_t)blockIdx.x * per_block, b1 = min(N, b0 + per_block);  // per_block % 256 == 0
     const uint32_t* Sq = S + (int64_t)ql * ld;
     unsigned long long* C = cand + (int64_t)ql * kCandCap;
-    for (int64_t wb = d0 + (int64_t)wave * kWave * 4; wb < d1; wb += 512 * 4) {
-        const int64_t d = wb + (int64_t)lane * 4;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (d < d1) v = *reinterpret_cast<const uint4*>(Sq + d);  // d + 3 < ld: rows are padded to 64
-        const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+    auto scan = [&](int64_t d0, int64_t d1) {  // d0 % 256 == 0
+        for (int64_t wb = d0 + (int64_t)wave * kWave * 4; wb < d1; wb += 512 * 4) {
+            const int64_t d = wb + (int64_t)lane * 4;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (d < d1) v = *reinterpret_cast<const uint4*>(Sq + d);  // d + 3 < ld: rows are padded to 64
+            const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const unsigned long long c = comp_key(vs[j], (uint32_t)(d + j));
-            const bool take = d + j < d1 && c >= lo;
-            const unsigned long long m = __ballot(take);
-            if (m == 0) continue;
-            int slot = 0;
-            if (lane == 0) slot = atomicAdd(&n_stage, __popcll(m));
-            slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
-            if (take && slot < kFilterStage) stage[slot] = c;
-            append_global(st, C, take && slot >= kFilterStage, c, lane);
+            for (int j = 0; j < 4; j++) {
+                const unsigned long long c = comp_key(vs[j], (uint32_t)(d + j));
+                const bool take = d + j < d1 && c >= lo;
+                const unsigned long long m = __ballot(take);
+                if (m == 0) continue;
+                int slot = 0;
+                if (lane == 0) slot = atomicAdd(&n_stage, __popcll(m));
+                slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
+                if (take && slot < kFilterStage) stage[slot] = c;
+                append_global(st, C, take && slot >= kFilterStage, c, lane);
+            }
         }
+    };
+    if (st->fused == 1 && seed_stride > 0) {
+        // fused filtering: the other tiles' candidates were appended while they were
+        // scored; only the seed tiles' documents are scanned here
+        for (int64_t t = b0 >> tile_shift; (t << tile_shift) < b1; t++)
+            if (t % seed_stride == 0) scan(max(b0, t << tile_shift), min(b1, (t + 1) << tile_shift));
+    } else {
+        scan(b0, b1);
     }
     __syncthreads();
     const int n = min(n_stage, kFilterStage);
@@ -519,8 +615,9 @@ __global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_
         for (int i = tid; i < m; i += 1024) bid[i] = (int32_t)(~(uint32_t)sel[i]);
         nb = m;
     } else {
-        const double tau = band_tau(sk, qb.delta[q], qb.q_abs_err[q]);
-        const unsigned long long lo = st->lo;
+            const double tau = band_tau(sk, qb.delta[q], qb.q_abs_err[q]);
+        // with fused filtering the other tiles' candidates start at the bound, the seed tiles' at lo
+        const unsigned long long lo = st->fused == 1 ? max(st->lo, st->bound) : st->lo;
         const double lo_val = (double)__uint_as_float((uint32_t)(lo >> 32));
         const bool inside = tau > 0.0 && (((uint32_t)lo == 0u) ? (lo_val <= tau) : (lo_val < tau));
         if (!inside) {
@@ -631,8 +728,24 @@ __global__ void k_diag(int32_t q0, int32_t qt, const SelState* __restrict__ stat
 
 }  // namespace
 
+hipError_t launch_seed_bound(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const Workspace& ws,
+                             hipStream_t s, int tile_shift, int stride) {
+    hipLaunchKernelGGL(k_seed_bound, dim3(qt), dim3(64), 0, s, qb, q0, ix.n_docs, (const uint32_t*)ws.hist1,
+                       ws.state);
+    GS_CHECK_LAUNCH("k_seed_bound");
+    const int64_t n_tiles = (ix.n_docs + (1ll << tile_shift) - 1) >> tile_shift;
+    const int64_t seeds = (n_tiles + stride - 1) / stride;
+    hipLaunchKernelGGL(k_seed_hist, dim3((unsigned)seeds, (unsigned)qt), dim3(512), 0, s, ix.n_docs,
+                       (const uint32_t*)ws.scores, ws.ld, tile_shift, stride, (const SelState*)ws.state, ws.hist_ref);
+    GS_CHECK_LAUNCH("k_seed_hist");
+    hipLaunchKernelGGL(k_seed_refine, dim3(qt), dim3(64), 0, s, ws.hist_ref, ws.state);
+    GS_CHECK_LAUNCH("k_seed_refine");
+    return hipSuccess;
+}
+
 hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const Workspace& ws,
-                         int32_t* out_ids, void* out_scores, int32_t* diag, hipStream_t s) {
+                         int32_t* out_ids, void* out_scores, int32_t* diag, hipStream_t s, int tile_shift,
+                         int seed_stride) {
     const int64_t N = ix.n_docs;
     const int per = 65536;
     const dim3 grid_scan((unsigned)((N + per - 1) / per), (unsigned)qt);
@@ -666,7 +779,7 @@ hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int
         GS_CHECK_LAUNCH("k_refine_select");
     }
     hipLaunchKernelGGL(k_filter, grid_scan, dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores, ws.ld, per, ws.state,
-                       ws.cand);
+                       ws.cand, seed_stride > 0 ? tile_shift : 16, seed_stride);
     GS_CHECK_LAUNCH("k_filter");
     hipError_t e = final_pass();
     if (e != hipSuccess) return e;
