@@ -53,6 +53,7 @@ def parse():
                     help="other precision[:kernel] forms to time (comma list, or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16, help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--profile", action="store_true", help="main form only, no CPU leg (for profiler runs)")
+    ap.add_argument("--no-fused", action="store_true", help="main form: scan every score row (no fused candidate filtering)")
     ap.add_argument("--batched", default="u8,bf16",
                     help="precisions for the 4,096-query uneven batch (autotuned, graph vs plain), or 'none'")
     ap.add_argument("--batched-queries", type=int, default=4096)
@@ -365,7 +366,7 @@ def main():
     queries = workload.make_queries(w, n=nq)
     log("collection: %d postings; queries: %d (mean nnz %.1f)" % (docs.nnz, nq, queries.nnz / max(nq, 1)))
     df = np.bincount(docs.terms, minlength=docs.vocab)
-    opts = gs.make_opts(args.kernel, tile_docs=args.tile_docs, chunk=args.chunk)
+    opts = gs.make_opts(args.kernel, tile_docs=args.tile_docs, chunk=args.chunk, fused_filter=not args.no_fused)
 
     # yardstick: a plain 2 GiB device copy (reads and writes exactly its size once)
     src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")

@@ -280,7 +280,8 @@ int32_t gs_autotune(gs_index index, gs_batch batch, void* workspace, size_t work
 /*
  * Per-query selection diagnostics of the last gs_search_batch on this batch
  * (host copy; call after the stream has been synchronised).
- * out [n_queries * 4] int32: candidates kept by the filter, refinement passes
+ * out [n_queries * 4] int32: candidates kept by the filter (with fused
+ * filtering: those appended while scoring plus the seed tiles'), refinement passes
  * over the score array, bf16 band size (0 for other precisions), and an
  * overflow flag (1 if the candidate buffer overflowed; the row is then
  * invalid and the search call must be repeated with a larger workspace).
@@ -290,9 +291,12 @@ int32_t gs_batch_diagnostics(gs_batch batch, int32_t* out);
 /*
  * Kernel timing for measurement. While enabled (on != 0), gs_search_batch
  * records a HIP event pair on its stream around every scoring launch and
- * around every selection (top-k) sequence. gs_timing_read synchronises those
- * events, returns the summed milliseconds and launch counts since the
- * previous read (any output pointer may be NULL) and releases the events.
+ * around every selection (top-k) sequence. With fused candidate filtering a
+ * scoring pass is two launches (seed tiles, then the rest), timed apart and
+ * counted as one; the seed bound between them is selection time.
+ * gs_timing_read synchronises those events, returns the summed milliseconds
+ * and launch counts since the previous read (any output pointer may be NULL)
+ * and releases the events.
  * Process-wide; thread-safe. Errors: GS_EHIP.
  */
 int32_t gs_timing_enable(int32_t on);

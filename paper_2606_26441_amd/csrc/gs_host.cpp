@@ -396,7 +396,8 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // ---- kernel timing (measurement only) ----
 struct TimedSpan {
     hipEvent_t a, b;
-    int kind;  // 0 scoring, 1 selection
+    int kind;     // 0 scoring, 1 selection
+    bool counts;  // counts as one launch of its kind
 };
 std::mutex g_timing_mu;
 bool g_timing_on = false;
@@ -410,9 +411,12 @@ bool timing_on() {
 struct SpanRecorder {
     TimedSpan span{};
     bool active = false;
-    SpanRecorder(int kind, hipStream_t s) {
+    // counts: whether the span counts as one launch of its kind (a scoring pass split into
+    // two launches records the first one without counting it)
+    SpanRecorder(int kind, hipStream_t s, bool counts = true) {
         if (kind < 0 || !timing_on()) return;
         span.kind = kind;
+        span.counts = counts;
         if (hipEventCreate(&span.a) != hipSuccess) return;
         if (hipEventCreate(&span.b) != hipSuccess) {
             (void)hipEventDestroy(span.a);
@@ -978,16 +982,30 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int
         const int32_t n = std::min(qt, nq - q0);
         hipError_t e = launch_clear(ws, n, s);
         if (e == hipSuccess && ix->n_docs > 0) {
-            SpanRecorder rec(timing ? 0 : -1, s);
-            if (so.kernel == GS_KERNEL_ATOMIC) e = launch_score_atomic(ix->dev, b->dev, q0, n, so, ws, s);
-            else if (so.kernel == GS_KERNEL_DOCPAR) e = launch_score_docpar(ix->dev, b->dev, q0, n, so, ws, s);
-            else if (so.seed_stride == 0) e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s);
-            else {
-                e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 1);  // seed tiles
-                if (e == hipSuccess) e = launch_seed_bound(ix->dev, b->dev, q0, n, ws, s, so.tile_shift, so.seed_stride);
-                if (e == hipSuccess) e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 2);  // the rest
+            if (so.seed_stride == 0 || (so.kernel != GS_KERNEL_TILED && so.kernel != GS_KERNEL_SHARED)) {
+                SpanRecorder rec(timing ? 0 : -1, s);
+                if (so.kernel == GS_KERNEL_ATOMIC) e = launch_score_atomic(ix->dev, b->dev, q0, n, so, ws, s);
+                else if (so.kernel == GS_KERNEL_DOCPAR) e = launch_score_docpar(ix->dev, b->dev, q0, n, so, ws, s);
+                else e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s);
+                rec.end(s);
+            } else {
+                // fused filtering: seed tiles, their bound (selection work), then the other tiles
+                {
+                    SpanRecorder rec(timing ? 0 : -1, s, false);
+                    e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 1);
+                    rec.end(s);
+                }
+                if (e == hipSuccess) {
+                    SpanRecorder rec(timing ? 1 : -1, s, false);
+                    e = launch_seed_bound(ix->dev, b->dev, q0, n, ws, s, so.tile_shift, so.seed_stride);
+                    rec.end(s);
+                }
+                if (e == hipSuccess) {
+                    SpanRecorder rec(timing ? 0 : -1, s);
+                    e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 2);
+                    rec.end(s);
+                }
             }
-            rec.end(s);
         }
         if (e == hipSuccess) {
             SpanRecorder rec(timing ? 1 : -1, s);
@@ -1219,7 +1237,7 @@ int32_t gs_timing_read(double* score_ms, int64_t* score_launches, double* select
         if (e == hipSuccess) e = hipEventElapsedTime(&t, sp.a, sp.b);
         if (e == hipSuccess) {
             ms[sp.kind] += t;
-            cnt[sp.kind] += 1;
+            cnt[sp.kind] += sp.counts ? 1 : 0;
         } else {
             err = e;
         }

@@ -170,10 +170,15 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
         reinterpret_cast<uint4*>(Sq)[i] = make_uint4(v[0], v[1], v[2], v[3]);
         const uint32_t d0 = (uint32_t)(base + 4 * i);
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const unsigned long long c = comp_key(v[j], d0 + j);
-            atomicAdd(&hist[(c >> fs) & (kHistBins - 1)], 1u);
-            if (append) append_candidates(c >= bound, c, st, C);
+        for (int j = 0; j < 4; j++) atomicAdd(&hist[(comp_key(v[j], d0 + j) >> fs) & (kHistBins - 1)], 1u);
+        // a composite reaches the bound only if its score bits reach the bound's: one test
+        // of the lane's largest score first, the exact per-document test only then
+        if (append && __ballot(max(max(v[0], v[1]), max(v[2], v[3])) >= (uint32_t)(bound >> 32))) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const unsigned long long c = comp_key(v[j], d0 + j);
+                append_candidates(c >= bound, c, st, C);
+            }
         }
     }
     for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {

@@ -163,9 +163,14 @@ __global__ __launch_bounds__(512) void k_seed_hist(int64_t N, const uint32_t* __
     const unsigned long long mask = (1ull << (shift - nshift)) - 1ull;
     const int64_t d0 = ((int64_t)blockIdx.x * stride) << tile_shift, d1 = min(N, d0 + (1ll << tile_shift));
     const uint32_t* Sq = S + (int64_t)ql * ld;
-    for (int64_t d = d0 + tid; d < d1; d += 512) {
-        const unsigned long long c = comp_key(Sq[d], (uint32_t)d);
-        if ((c >> shift) == want) atomicAdd(&hist[(c >> nshift) & mask], 1u);
+    for (int64_t d = d0 + 4 * tid; d < d1; d += 4 * 512) {
+        const uint4 v = *reinterpret_cast<const uint4*>(Sq + d);  // d + 3 < ld: rows are padded to 64
+        const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const unsigned long long c = comp_key(vs[j], (uint32_t)(d + j));
+            if (d + j < d1 && (c >> shift) == want) atomicAdd(&hist[(c >> nshift) & mask], 1u);
+        }
     }
     __syncthreads();
     for (int b = tid; b < kHistBins; b += 512)
