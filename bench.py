@@ -66,15 +66,17 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(df, queries, n_docs, wbytes, idbytes):
+def algorithmic_bytes(df, queries, n_docs, wbytes, idbytes, written_docs=None):
     """Per-query postings of the query's terms (doc id + weight) and one score-array write / read.
 
     The doc-tiled kernels read a 16-bit in-tile doc offset (idbytes 2); the global-atomic
-    kernel reads the 32-bit doc id (idbytes 4).
+    kernel reads the 32-bit doc id (idbytes 4). With fused candidate filtering (fp32, uint8)
+    only the seed tiles' scores are written (written_docs per query).
     """
     p_q = np.array([int(df[queries.row(i)[0]].sum()) for i in range(queries.n_rows)], dtype=np.int64)
-    score_kernel = int(p_q.sum()) * (idbytes + wbytes) + queries.n_rows * n_docs * 4
-    step = score_kernel + queries.n_rows * n_docs * 4
+    wd = n_docs if written_docs is None else written_docs
+    score_kernel = int(p_q.sum()) * (idbytes + wbytes) + queries.n_rows * wd * 4
+    step = score_kernel + queries.n_rows * wd * 4  # the filter reads what was written
     return p_q, score_kernel, step
 
 
@@ -387,8 +389,15 @@ def main():
     log("main form: %s / %s, %d warmup + %d timed steps" % (args.precision, args.kernel, args.warmup, args.steps))
     main_res = time_form(gs, torch, docs, queries, args.k, args.precision, opts, args.steps, args.warmup,
                          keep_forward=(args.kernel == "docpar"))
+    written = None
+    tile_docs = args.tile_docs or (8192 if args.precision == "fp32" else 16384)
+    n_tiles = (n_docs + tile_docs - 1) // tile_docs
+    if (not args.no_fused and args.kernel in ("tiled", "shared") and args.precision != "bf16" and nq >= 32
+            and args.k <= 1024 and n_tiles >= 16):
+        # fused candidate filtering: score rows of the seed tiles (every 8th) only
+        written = sum(min(tile_docs, n_docs - t * tile_docs) for t in range(0, n_tiles, 8))
     p_q, score_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision],
-                                                   2 if args.kernel in ("tiled", "shared") else 4)
+                                                   2 if args.kernel in ("tiled", "shared") else 4, written)
     if args.kernel == "docpar":
         # document-parallel: every forward row (term id + fp32 weight) per query, plus one score write
         score_bytes = nq * (docs.nnz * 8 + n_docs * 4)

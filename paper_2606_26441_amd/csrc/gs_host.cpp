@@ -455,7 +455,8 @@ size_t workspace_bytes(int64_t n_docs, int32_t qt, int32_t precision) {
     b += align256(((size_t)qt * kMaxQueryNnz + 1) * 8);
     b += align256((size_t)qt * kMaxQueryNnz * 4);
     b += align256((size_t)qt * 4);
-    b += align256(8 * 4);
+    b += align256(16 * 4);
+    b += align256((size_t)qt * 4);
     return b;
 }
 
@@ -482,7 +483,8 @@ void carve_workspace(void* base, int64_t n_docs, int32_t qt, int32_t precision, 
     ws->work_prefix = (int64_t*)take(((size_t)qt * kMaxQueryNnz + 1) * 8);
     ws->work_pair_q = (int32_t*)take((size_t)qt * kMaxQueryNnz * 4);
     ws->order = (int32_t*)take((size_t)qt * 4);
-    ws->counters = (uint32_t*)take(8 * 4);
+    ws->counters = (uint32_t*)take(16 * 4);
+    ws->rescore_list = (int32_t*)take((size_t)qt * 4);
 }
 
 }  // namespace gs
@@ -1009,8 +1011,11 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int
         }
         if (e == hipSuccess) {
             SpanRecorder rec(timing ? 1 : -1, s);
+            std::function<hipError_t()> rescore;
+            if (so.seed_stride > 0 && ix->precision != kBF16)
+                rescore = [&] { return launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 3); };
             e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s, so.tile_shift,
-                              so.seed_stride);
+                              so.seed_stride, rescore);
             rec.end(s);
         }
         if (e != hipSuccess)

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 
 struct gs_batch_s;
@@ -103,6 +104,8 @@ struct SelState {
     unsigned long long bound;
     int32_t fused;              // 1 while the appended candidates stand in for the row scan
     int32_t fused_over;         // the appends passed kFusedCap
+    int32_t rescore;            // fell back after its non-seed rows were left unwritten: score them again
+    int32_t pad_;
 };
 
 // Workspace carve-up for a tile of qt queries.
@@ -117,7 +120,9 @@ struct Workspace {
     int64_t* work_prefix;         // [qt * kMaxQueryNnz + 1] (atomic kernel)
     int32_t* work_pair_q;         // [qt * kMaxQueryNnz]
     int32_t* order;               // [qt] persistent kernel: query order within the tile
-    uint32_t* counters;           // [8] persistent kernel: per-XCD work counters
+    uint32_t* counters;           // [16]: [0..7] persistent kernel per-XCD work counters,
+                                  // [8] queries in rescore_list
+    int32_t* rescore_list;        // [qt] fused filtering: queries whose rows are scored again
     int64_t ld;                   // row stride of the score arrays (n_docs rounded up to 64)
 };
 
@@ -134,7 +139,9 @@ struct ScoreOpts {
 };
 
 // Doc tiles of a scoring launch: phase 0 all tiles, phase 1 the seed tiles
-// (multiples of stride), phase 2 the others. v is the launch's tile index.
+// (multiples of stride), phase 2 the others, phase 3 the others again for the
+// queries that fell back from fused filtering (their rows). v is the launch's
+// tile index.
 __host__ __device__ inline int64_t phase_tiles(int phase, int stride, int64_t n_tiles) {
     if (phase == 0) return n_tiles;
     const int64_t seeds = (n_tiles + stride - 1) / stride;
@@ -169,7 +176,8 @@ hipError_t launch_fill(void* p, int64_t n_words, uint32_t v, hipStream_t s);  //
 // ---- launchers (gs_topk.hip) ----
 hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                          const Workspace& ws, int32_t* out_ids, void* out_scores, int32_t* diag,
-                         hipStream_t s, int tile_shift = 0, int seed_stride = 0);
+                         hipStream_t s, int tile_shift = 0, int seed_stride = 0,
+                         const std::function<hipError_t()>& after_first = nullptr);
 // fused filtering: the bound of every query of the tile from its seed-tile histogram
 hipError_t launch_seed_bound(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                              const Workspace& ws, hipStream_t s, int tile_shift, int stride);

@@ -147,10 +147,12 @@ __device__ __forceinline__ void append_candidates(bool take, unsigned long long 
     if (take && slot < kFusedCap) C[slot] = c;
 }
 
+// write: store the scores in the row; count: add the tile to the first-digit histogram.
 template <int BS, int AF>
 __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, int tile_n, int64_t base, uint32_t* Sq,
                                            int fs, double scale, uint32_t* hist_out, bool append,
-                                           unsigned long long bound, SelState* st, unsigned long long* C) {
+                                           unsigned long long bound, SelState* st, unsigned long long* C,
+                                           bool write, bool count) {
     const int tid = threadIdx.x;
     const int n4 = tile_n >> 2;
     for (int i = tid; i < n4; i += BS) {
@@ -167,10 +169,12 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
                 for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)v[j] * scale));
             }
         }
-        reinterpret_cast<uint4*>(Sq)[i] = make_uint4(v[0], v[1], v[2], v[3]);
+        if (write) reinterpret_cast<uint4*>(Sq)[i] = make_uint4(v[0], v[1], v[2], v[3]);
         const uint32_t d0 = (uint32_t)(base + 4 * i);
+        if (count) {
 #pragma unroll
-        for (int j = 0; j < 4; j++) atomicAdd(&hist[(comp_key(v[j], d0 + j) >> fs) & (kHistBins - 1)], 1u);
+            for (int j = 0; j < 4; j++) atomicAdd(&hist[(comp_key(v[j], d0 + j) >> fs) & (kHistBins - 1)], 1u);
+        }
         // a composite reaches the bound only if its score bits reach the bound's: one test
         // of the lane's largest score first, the exact per-document test only then
         if (append && __ballot(max(max(v[0], v[1]), max(v[2], v[3])) >= (uint32_t)(bound >> 32))) {
@@ -186,11 +190,12 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
         if constexpr (AF == kAccFx64) v = __float_as_uint((float)((double)((const unsigned long long*)acc_v)[i] * scale));
         else if constexpr (AF == kAccFx32) v = __float_as_uint((float)((double)((const uint32_t*)acc_v)[i] * scale));
         else v = ((const uint32_t*)acc_v)[i];
-        Sq[i] = v;
+        if (write) Sq[i] = v;
         const unsigned long long c = comp_key(v, (uint32_t)(base + i));
-        atomicAdd(&hist[(c >> fs) & (kHistBins - 1)], 1u);
+        if (count) atomicAdd(&hist[(c >> fs) & (kHistBins - 1)], 1u);
         if (append) append_candidates(c >= bound, c, st, C);
     }
+    if (!count) return;
     __syncthreads();
     for (int b = tid; b < kHistBins; b += BS)
         if (hist[b]) atomicAdd(&hist_out[b], hist[b]);
@@ -256,7 +261,7 @@ __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* ta
 template <int P, int TS, int CH, bool RB>
 __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& qb, int32_t q0, int64_t tile, int ql,
                                            uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
-                                           uint32_t* lds, TileShared& sh, bool append, SelState* state,
+                                           uint32_t* lds, TileShared& sh, int phase, SelState* state,
                                            unsigned long long* cand) {
     constexpr int BS = 512, NW = BS / kWave, TILE = 1 << TS, U = CH / kWave, GPT = TS - kGrainShift;
     constexpr bool FX = P != kU8;                  // fixed-point products (fp32, bf16)
@@ -270,6 +275,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: chunk bookkeeping stays scalar
     const int q = q0 + ql;
     if (qb.k[q] == 0) return;  // nothing is selected for it (also every padding slot of a batch)
+    if (phase == 3 && state[ql].rescore != 1) return;  // only the queries that fell back
     const int64_t N = ix.n_docs;
     const int64_t base = tile << TS;
     const int tile_n = (int)min((int64_t)TILE, N - base);
@@ -420,12 +426,16 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     __syncthreads();
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
     __syncthreads();
-    // fused filtering (the non-seed tiles of a query whose seed bound is set): append while flushing
+    // Fused filtering (the non-seed tiles of a query whose seed bound is set): append while
+    // flushing, no appends once past the cap, and no score row for fp32 and uint8 (bf16 keeps
+    // them for its band check). A query that falls back gets its rows from phase 3.
     SelState* st = state + ql;
-    const bool app = append && st->fused == 1 && !st->fused_over;  // no appends once past the cap
+    const bool fused_q = phase == 2 && st->fused == 1;
+    const bool app = fused_q && !st->fused_over;
+    const bool write = !fused_q || P == kBF16;
     flush_tile<BS, AF>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
                        FX ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins, app, app ? st->bound : 0ull, st,
-                       cand + (int64_t)ql * kCandCap);
+                       cand + (int64_t)ql * kCandCap, write, phase != 3);
 }
 
 // Per-query form: grid (tiles, queries), the tiles of one query are consecutive
@@ -435,11 +445,22 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
 template <int P, int TS, int CH, bool RB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_tiled(
     DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
-    int phase, int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand) {
+    int phase, int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand,
+    const uint32_t* __restrict__ counters, const int32_t* __restrict__ rescore_list) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ TileShared sh;
-    score_tile<P, TS, CH, RB>(ix, qb, q0, phase_tile(phase, stride, (int64_t)blockIdx.x), (int)blockIdx.y, S, ld,
-                              hist1, lds, sh, phase == 2, state, cand);
+    const int64_t tile = phase_tile(phase, stride, (int64_t)blockIdx.x);
+    if (phase != 3) {
+        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state, cand);
+        return;
+    }
+    // rows of the queries that fell back from fused filtering (usually none): one
+    // workgroup per tile walks the list
+    const int nres = (int)counters[8];
+    for (int r = 0; r < nres; r++) {
+        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, rescore_list[r], S, ld, hist1, lds, sh, phase, state, cand);
+        __syncthreads();
+    }
 }
 
 // Persistent form of the shared traversal: a grid of (resident workgroups,
@@ -452,22 +473,25 @@ template <int P, int TS, int CH, bool RB>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_persistent(
     DevIndex ix, DevBatch qb, int32_t q0, int32_t qt, const int32_t* __restrict__ order,
     uint32_t* __restrict__ counters, uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1, int phase,
-    int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand) {
+    int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand,
+    const int32_t* __restrict__ rescore_list) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ TileShared sh;
     __shared__ int64_t item_sh;
     const int x = (int)(blockIdx.x & 7);
     const int64_t n_tiles = phase_tiles(phase, stride, (ix.n_docs + (1 << TS) - 1) >> TS);
     const int64_t tiles_x = n_tiles > x ? (n_tiles - x + 7) / 8 : 0;
-    const int64_t items = tiles_x * qt;
+    // phase 3 covers only the queries that fell back from fused filtering (usually none)
+    const int nq = phase == 3 ? (int)counters[8] : qt;
+    const int64_t items = tiles_x * nq;
     for (;;) {
         if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(&counters[x], 1u);
         __syncthreads();
         const int64_t item = item_sh;
         if (item >= items) break;
-        const int64_t tile = phase_tile(phase, stride, x + 8 * (item / qt));
-        const int ql = order[item % qt];
-        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh, phase == 2, state, cand);
+        const int64_t tile = phase_tile(phase, stride, x + 8 * (item / nq));
+        const int ql = phase == 3 ? rescore_list[item % nq] : order[item % nq];
+        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh, phase, state, cand);
         __syncthreads();
     }
 }
@@ -681,8 +705,9 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         }
     }
     if (!persistent) {
-        hipLaunchKernelGGL((k_score_tiled<P, TS, CH, RB>), dim3((unsigned)n_tiles, (unsigned)qt), dim3(512), lds, s, ix,
-                           qb, q0, ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand);
+        hipLaunchKernelGGL((k_score_tiled<P, TS, CH, RB>), dim3((unsigned)n_tiles, phase == 3 ? 1u : (unsigned)qt),
+                           dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand,
+                           (const uint32_t*)ws.counters, (const int32_t*)ws.rescore_list);
         GS_CHECK_LAUNCH("k_score_tiled");
         return hipSuccess;
     }
@@ -697,7 +722,7 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         return std::max(8, (p.multiProcessorCount * std::max(per_cu, 1)) / 8 * 8);
     }();
     if (grid <= 0) return hipErrorInvalidConfiguration;
-    if (phase != 2) {  // the second launch of a fused search keeps the first one's order
+    if (phase <= 1) {  // the later launches of a fused search keep the first one's order
         hipLaunchKernelGGL(k_work_order, dim3((unsigned)((qt + 255) / 256)), dim3(256), 0, s, qb, q0, qt, ws.order);
         GS_CHECK_LAUNCH("k_work_order");
     } else {
@@ -706,7 +731,7 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
     }
     hipLaunchKernelGGL((k_score_persistent<P, TS, CH, RB>), dim3((unsigned)grid), dim3(512), lds, s, ix, qb, q0, qt,
                        (const int32_t*)ws.order, ws.counters, ws.scores, ld, ws.hist1, phase, stride, ws.state,
-                       ws.cand);
+                       ws.cand, (const int32_t*)ws.rescore_list);
     GS_CHECK_LAUNCH("k_score_persistent");
     return hipSuccess;
 }
@@ -744,7 +769,7 @@ hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s)
 }
 
 hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s) {
-    hipError_t e = fill_u32(ws.counters, 8, s);
+    hipError_t e = fill_u32(ws.counters, 16, s);
     if (e == hipSuccess) e = fill_u32(ws.hist1, (int64_t)qt * kHistBins, s);
     if (e == hipSuccess) e = fill_u32(ws.hist_ref, (int64_t)qt * kHistBins, s);
     if (e == hipSuccess) e = fill_u32(ws.state, (int64_t)qt * sizeof(SelState) / 4, s);

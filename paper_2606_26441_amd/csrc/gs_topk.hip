@@ -76,7 +76,8 @@ __device__ __forceinline__ int64_t kq_of(const DevBatch& qb, int q, int64_t N) {
 }
 
 __global__ __launch_bounds__(64) void k_select_first(DevBatch qb, int32_t q0, int64_t N, int precision,
-                                                     const uint32_t* __restrict__ hist1, SelState* __restrict__ state) {
+                                                     const uint32_t* __restrict__ hist1, SelState* __restrict__ state,
+                                                     uint32_t* __restrict__ counters, int32_t* __restrict__ rescore_list) {
     const int ql = blockIdx.x, q = q0 + ql;
     SelState* st = state + ql;
     const int64_t kq = kq_of(qb, q, N);
@@ -114,6 +115,10 @@ __global__ __launch_bounds__(64) void k_select_first(DevBatch qb, int32_t q0, in
     if (st->fused == 1 && (st->resolved != 1 || st->fused_over || (int64_t)st->n_cand + kept > kCandCap)) {
         st->fused = 0;
         st->n_cand = 0;
+        if (precision != kBF16) {  // its non-seed rows were not written: score them again
+            st->rescore = 1;
+            rescore_list[atomicAdd(&counters[8], 1u)] = ql;
+        }
     }
 }
 
@@ -750,13 +755,17 @@ hipError_t launch_seed_bound(const DevIndex& ix, const DevBatch& qb, int32_t q0,
 
 hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const Workspace& ws,
                          int32_t* out_ids, void* out_scores, int32_t* diag, hipStream_t s, int tile_shift,
-                         int seed_stride) {
+                         int seed_stride, const std::function<hipError_t()>& after_first) {
     const int64_t N = ix.n_docs;
     const int per = 65536;
     const dim3 grid_scan((unsigned)((N + per - 1) / per), (unsigned)qt);
     hipLaunchKernelGGL(k_select_first, dim3(qt), dim3(64), 0, s, qb, q0, N, ix.precision,
-                       (const uint32_t*)ws.hist1, ws.state);
+                       (const uint32_t*)ws.hist1, ws.state, ws.counters, ws.rescore_list);
     GS_CHECK_LAUNCH("k_select_first");
+    if (after_first) {  // fused filtering: rows for the queries that fell back
+        const hipError_t e = after_first();
+        if (e != hipSuccess) return e;
+    }
     auto final_pass = [&]() -> hipError_t {
         switch (ix.precision) {
             case kFP32:
