@@ -96,11 +96,12 @@ typedef struct gs_search_opts {
                             GS_EUNSUPPORTED) */
     int32_t chunk;       /* postings per work item (TILED/ATOMIC): 0 (default),
                             64, 128, 256, 512 or 1024 */
-    int32_t group;       /* queries per workgroup (SHARED): 0 (default) or 1..8 */
-    int32_t no_fused_filter; /* TILED/SHARED: 0 (default) appends candidates while scoring
-                                (a bound from every 8th doc tile, then only those tiles'
-                                scores are scanned); 1 scans every score row */
-    int32_t reserved[2]; /* must be 0 */
+    int32_t no_fused_filter; /* TILED/SHARED, searches of 32+ queries: 0 (default)
+                                appends candidates while scoring (a bound from every
+                                8th doc tile, then only those tiles' scores are
+                                scanned and, for fp32 and uint8, written); 1 writes
+                                and scans every score row */
+    int32_t reserved[3]; /* must be 0 */
 } gs_search_opts;
 
 typedef struct gs_index_info_t {

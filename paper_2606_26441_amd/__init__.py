@@ -44,8 +44,7 @@ _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error"
 
 class SearchOpts(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("query_tile", ctypes.c_int32), ("tile_docs", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("group", ctypes.c_int32), ("no_fused_filter", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("chunk", ctypes.c_int32), ("no_fused_filter", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -144,10 +143,10 @@ def _stream_ptr(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_opts(kernel="auto", query_tile=0, tile_docs=0, chunk=0, group=0, fused_filter=True) -> SearchOpts:
+def make_opts(kernel="auto", query_tile=0, tile_docs=0, chunk=0, fused_filter=True) -> SearchOpts:
     o = SearchOpts()
     o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
-    o.query_tile, o.tile_docs, o.chunk, o.group = int(query_tile), int(tile_docs), int(chunk), int(group)
+    o.query_tile, o.tile_docs, o.chunk = int(query_tile), int(tile_docs), int(chunk)
     o.no_fused_filter = 0 if fused_filter else 1
     return o
 

@@ -890,10 +890,9 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
     // 64 KiB of LDS accumulators: 8192 fixed-point (fp32, bf16) or 16384 int32 (uint8) documents
     so->tile_shift = ix->precision == kFP32 ? 13 : 14;
     so->chunk = 1024;  // measured fastest for both doc-tiled forms at every tile size
-    so->group = 4;
     so->seed_stride = 1;  // fused filtering wanted (the stride itself is chosen per search)
     if (!o) return GS_OK;
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < 3; i++)
         if (o->reserved[i] != 0) return fail(GS_EINVAL, "reserved option fields must be 0");
     if (o->no_fused_filter != 0 && o->no_fused_filter != 1) return fail(GS_EINVAL, "no_fused_filter must be 0 or 1");
     if (o->no_fused_filter) so->seed_stride = 0;
@@ -916,8 +915,6 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
         case 64: case 128: case 256: case 512: case 1024: so->chunk = o->chunk; break;
         default: return fail(GS_EINVAL, "chunk must be 0, 64, 128, 256, 512 or 1024");
     }
-    if (o->group < 0 || o->group > 8) return fail(GS_EINVAL, "group must be in [0, 8]");
-    if (o->group) so->group = o->group;
     return GS_OK;
 }
 

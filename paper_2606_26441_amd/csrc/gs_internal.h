@@ -133,7 +133,6 @@ struct ScoreOpts {
     int kernel;
     int tile_shift;   // doc tile of the TILED/SHARED kernels = 1 << tile_shift docs
     int chunk;        // postings per work item
-    int group;
     int raise = 1;    // fixed point: some positive product of the batch may round to 0 units
     int seed_stride = 0;  // fused candidate filtering: every seed_stride-th doc tile seeds the bound (0: off)
 };

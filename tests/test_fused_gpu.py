@@ -121,3 +121,22 @@ def test_fused_graph_replays(data):
         assert np.array_equal(ids.cpu().numpy(), direct[rep][0]) and np.array_equal(sc.cpu().numpy(), direct[rep][1])
     graph.close()
     idx.close()
+
+
+@pytest.mark.parametrize("n_terms", [(1, 8), (1, 20)])
+def test_fused_bf16_band_below_the_candidates(n_terms):
+    # dyadic weights (exact in bf16) give many equal scores near the k-th: the bf16 error band
+    # then reaches below the fused candidates of some queries, whose rows are scored again
+    # before the band pass; fallbacks and fused queries must all equal the row scan
+    gs, torch = _gs()
+    rng = np.random.default_rng(65 + n_terms[1])
+    dy = lambda r, n: r.integers(1, 13, n) / 4.0
+    docs = random_rows(rng, 300_000, 200, n_terms[0], n_terms[1], weight_fn=dy)
+    qs = random_rows(rng, 40, 200, 3, 12, weight_fn=dy)
+    idx = gs.Index.from_rows(docs, "bf16")
+    for kernel in ("tiled", "shared"):
+        a = _search(gs, torch, idx, qs, 1000, 1000, kernel, True)
+        b = _search(gs, torch, idx, qs, 1000, 1000, kernel, False)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), kernel
+    check_batch("bf16", docs, qs.subset(np.arange(6)), a[0][:6], a[1][:6], 1000, what="bf16 band")
+    idx.close()
