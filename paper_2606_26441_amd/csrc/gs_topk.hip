@@ -210,8 +210,7 @@ __global__ __launch_bounds__(64) void k_seed_refine(uint32_t* __restrict__ hist_
 }
 
 __global__ __launch_bounds__(512) void k_refine_hist(int32_t q0, int64_t N, const uint32_t* __restrict__ S, int64_t ld,
-                                                     int per_block, const SelState* __restrict__ state,
-                                                     uint32_t* __restrict__ hist_ref) {
+                                                     const SelState* __restrict__ state, uint32_t* __restrict__ hist_ref) {
     __shared__ uint32_t hist[kHistBins];
     const int ql = blockIdx.y;
     const SelState st = state[ql];
@@ -222,9 +221,10 @@ __global__ __launch_bounds__(512) void k_refine_hist(int32_t q0, int64_t N, cons
     const int shift = st.shift, nshift = max(shift - kHistBits, 0);
     const unsigned long long want = st.prefix >> shift;
     const unsigned long long mask = (1ull << (shift - nshift)) - 1ull;
-    const int64_t d0 = (int64_t)blockIdx.x * per_block, d1 = min(N, d0 + per_block);
+    // a few workgroups per query stride over the row: the launch stays cheap when
+    // no query needs a refinement (the usual case)
     const uint32_t* Sq = S + (int64_t)ql * ld;
-    for (int64_t d = d0 + tid; d < d1; d += 512) {
+    for (int64_t d = (int64_t)blockIdx.x * 512 + tid; d < N; d += (int64_t)gridDim.x * 512) {
         const unsigned long long c = comp_key(Sq[d], (uint32_t)d);
         if ((c >> shift) == want) atomicAdd(&hist[(c >> nshift) & mask], 1u);
     }
@@ -795,8 +795,8 @@ hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int
     };
     if (N == 0) return final_pass();  // empty collection: padding only
     for (int p = 0; p < kRefinePasses; p++) {
-        hipLaunchKernelGGL(k_refine_hist, grid_scan, dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores, ws.ld, per,
-                           (const SelState*)ws.state, ws.hist_ref);
+        hipLaunchKernelGGL(k_refine_hist, dim3(8, (unsigned)qt), dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores,
+                           ws.ld, (const SelState*)ws.state, ws.hist_ref);
         GS_CHECK_LAUNCH("k_refine_hist");
         hipLaunchKernelGGL(k_refine_select, dim3(qt), dim3(64), 0, s, qb, q0, N, ws.hist_ref, ws.state);
         GS_CHECK_LAUNCH("k_refine_select");
