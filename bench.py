@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -80,10 +81,26 @@ def algorithmic_bytes(df, queries, n_docs, wbytes, idbytes, written_docs=None):
     return p_q, score_kernel, step
 
 
-def profiled_traffic(kernel, precision, workload_name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel source is unchanged."""
-    import glob
+_C_TOKEN = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'', re.S)
+
+
+def code_digest(files):
+    """sha256 of C/HIP sources with comments removed and whitespace collapsed.
+
+    A comment edit leaves it unchanged; any change to the code itself changes it.
+    """
     import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        src = open(os.path.join(ROOT, f)).read()
+        src = _C_TOKEN.sub(lambda m: m.group(0) if m.group(0)[0] in "\"'" else " ", src)
+        h.update(" ".join(src.split()).encode())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel, precision, workload_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel code is unchanged."""
+    import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         text = open(path).read()
         if "```json" not in text:
@@ -91,10 +108,7 @@ def profiled_traffic(kernel, precision, workload_name):
         meta = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
         if (meta.get("kernel"), meta.get("precision"), meta.get("workload")) != (kernel, precision, workload_name):
             continue
-        h = hashlib.sha256()
-        for f in meta["source_files"]:
-            h.update(open(os.path.join(ROOT, f), "rb").read())
-        if h.hexdigest() == meta["source_sha256"]:
+        if code_digest(meta["source_files"]) == meta["code_sha256"]:
             return int(meta["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
 

@@ -2,7 +2,7 @@
 //   S[q][d] = sum over the query's terms t of w_q(t) * w_d(t)
 // (paper Sec. 4.1: the score decomposes into one scatter-add per query term).
 //
-// Three forms:
+// Forms:
 //  * k_score_tiled  - term-parallel, work = (query, doc tile). Each query term's
 //    posting list is doc-sorted, so the postings that fall into a doc tile are
 //    one contiguous segment (found in the per-term segment table). The
@@ -11,6 +11,9 @@
 //    writes the tile once (coalesced) and builds the histogram of the first
 //    selection digit. No global atomics, no zeroing pass. This is the hybrid
 //    of scatter-add and on-chip accumulation listed as future work (1) in Sec. 8.
+//  * k_score_persistent - the same work items on a resident grid, taken tile by
+//    tile (all queries of a tile on one XCD while its postings sit in that L2):
+//    the shared traversal of a batch.
 //  * k_score_atomic - term-parallel, work = (query, term, chunk of postings);
 //    global atomic adds into a zeroed score array, as in the paper's Sec. 5.2
 //    kernel (one program per query term looping over posting chunks), with
@@ -19,9 +22,13 @@
 //    over the doc's forward row with the query's weights in a dense LDS table;
 //    each output cell is written once, no atomics.
 //
-// Weight forms: fp32; bf16 (stored as the upper 16 bits of the fp32 pattern,
-// widened exactly, fp32 products and accumulation); uint8 impacts with int32
-// products and accumulation (exact).
+// Weight forms of the doc-tiled kernels: fp32 (products rounded to units of a
+// per-query scale and summed exactly in 64-bit fixed point), bf16 (stored as the
+// upper 16 bits of the fp32 pattern; 32-bit fixed point, then fp64 rescoring of
+// the candidates) and uint8 impacts (int32 products and sums, exact). With fused
+// candidate filtering a search runs them in phases: the seed tiles, then the
+// other tiles appending candidates at or above a bound while they flush, then a
+// pass that writes the rows of the queries that fell back (see gs_topk.hip).
 #include <algorithm>
 #include <type_traits>
 
