@@ -162,7 +162,7 @@ def score_error(oracle, docs, queries, s, k, rid, results):
     return out
 
 
-def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_forward=False):
+def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_forward=False, host_steps=0):
     idx = gs.Index.from_rows(docs, precision, keep_forward=keep_forward)
     batch = idx.batch(queries, k)
     nq = queries.n_rows
@@ -187,6 +187,16 @@ def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_
     diag = batch.diagnostics()
     res = {"ids": ids.cpu().numpy(), "scores": sc.cpu().numpy(), "total_ms": total_ms, "step_ms": step_ms,
            "timing": t, "diag": diag, "device_bytes": int(idx.info().device_bytes), "ws_bytes": ws.numel()}
+    if host_steps:
+        # host CSR in (validation, per-query scales, upload), results copied back to host memory
+        host_ms = []
+        for _ in range(host_steps):
+            t0 = time.perf_counter()
+            hi, hs = idx.search_host(queries, k, workspace=ws, opts=opts)
+            hi, hs = hi.cpu().numpy(), hs.cpu().numpy()
+            host_ms.append((time.perf_counter() - t0) * 1e3)
+            assert np.array_equal(hi, res["ids"]) and np.array_equal(hs, res["scores"]), "host-CSR search differs"
+        res["host_ms"] = np.array(host_ms)
     del ws, ids, sc
     batch.close()
     idx.close()
@@ -402,7 +412,7 @@ def main():
 
     log("main form: %s / %s, %d warmup + %d timed steps" % (args.precision, args.kernel, args.warmup, args.steps))
     main_res = time_form(gs, torch, docs, queries, args.k, args.precision, opts, args.steps, args.warmup,
-                         keep_forward=(args.kernel == "docpar"))
+                         keep_forward=(args.kernel == "docpar"), host_steps=0 if args.profile else 3)
     written = None
     tile_docs = args.tile_docs or (8192 if args.precision == "fp32" else 16384)
     n_tiles = (n_docs + tile_docs - 1) // tile_docs
@@ -425,9 +435,12 @@ def main():
     log("QPS %.1f  ms/step %.2f  score %.2f ms  select %.2f ms  score kernel %.0f GB/s"
         % (qps, ms_per_step, score_ms, select_ms, achieved))
 
+    kernel_name = {"tiled": "k_score_tiled", "shared": "k_score_persistent", "atomic": "k_score_atomic",
+                   "docpar": "k_score_docpar"}[args.kernel]
     traffic, traffic_src = (None, None)
-    if args.kernel == "tiled" and args.n_docs in (0, w.n_docs) and nq == w.n_queries:
-        traffic, traffic_src = profiled_traffic("k_score_tiled", args.precision, w.name)
+    if args.n_docs in (0, w.n_docs) and nq == w.n_queries and args.k == 1000 and not args.no_fused \
+            and not args.tile_docs and not args.chunk:
+        traffic, traffic_src = profiled_traffic(kernel_name, args.precision, w.name)
     out = {
         "metric": METRIC,
         "value": round(qps, 2),
@@ -442,11 +455,10 @@ def main():
         "dtype": DTYPE[args.precision],
         "data": "synthetic (seeded Zipf(1.1)/Poisson/lognormal stand-in for MS MARCO + SPLADE)",
         "config": {"workload": w.name, "n_docs": n_docs, "postings": docs.nnz, "batch": nq, "k": args.k,
-                   "precision": args.precision, "kernel": args.kernel, "tile_docs": args.tile_docs or (16384 if args.precision == "u8" else 8192),
+                   "precision": args.precision, "kernel": args.kernel, "tile_docs": tile_docs,
                    "chunk": args.chunk or 1024, "query_nnz_mean": round(queries.nnz / max(nq, 1), 2),
                    "postings_per_query_mean": int(p_q.mean())},
-        "roofline": {"bound": "hbm", "kernel": {"tiled": "k_score_tiled", "shared": "k_score_persistent",
-                                                "atomic": "k_score_atomic", "docpar": "k_score_docpar"}[args.kernel],
+        "roofline": {"bound": "hbm", "kernel": kernel_name,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_source": traffic_src,
@@ -458,6 +470,11 @@ def main():
                  "hbm_frac_whole_step": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "memory": {"index_bytes": main_res["device_bytes"], "workspace_bytes": main_res["ws_bytes"]},
         "hbm_copy_GBs": round(copy_gbs, 1),
+        "host_io": None if "host_ms" not in main_res else {
+            "qps": round(nq / (float(np.median(main_res["host_ms"])) / 1e3), 2),
+            "ms_per_batch": round(float(np.median(main_res["host_ms"])), 3),
+            "what": "gs_search from a host CSR (validation + upload), results copied to host; median of %d"
+                    % len(main_res["host_ms"])},
         "selection": {"candidates_mean": float(main_res["diag"][:, 0].mean()),
                       "refine_passes_max": int(main_res["diag"][:, 1].max()),
                       "overflow": int(main_res["diag"][:, 3].max())},
