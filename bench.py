@@ -70,13 +70,17 @@ def parse():
 def algorithmic_bytes(df, queries, n_docs, wbytes, idbytes, written_docs=None):
     """Per-query postings of the query's terms (doc id + weight) and one score-array write / read.
 
-    The doc-tiled kernels read a 16-bit in-tile doc offset (idbytes 2); the global-atomic
-    kernel reads the 32-bit doc id (idbytes 4). With fused candidate filtering (fp32, uint8)
-    only the seed tiles' scores are written (written_docs per query).
+    idbytes: bytes per posting for the doc id, a number or one per term. The doc-tiled
+    kernels read a 16-bit doc offset (2), or with fp32/bf16 weights in the per-query
+    kernel, for terms in byte form, 1 byte plus a 4-byte base per 64 postings; the
+    global-atomic kernel reads the 32-bit doc id (4). With fused candidate filtering
+    (fp32, uint8) only the seed tiles' scores are written (written_docs per query).
     """
     p_q = np.array([int(df[queries.row(i)[0]].sum()) for i in range(queries.n_rows)], dtype=np.int64)
+    per_term = df * (np.broadcast_to(np.asarray(idbytes, dtype=np.float64), df.shape) + wbytes)
+    post_bytes = sum(float(per_term[queries.row(i)[0]].sum()) for i in range(queries.n_rows))
     wd = n_docs if written_docs is None else written_docs
-    score_kernel = int(p_q.sum()) * (idbytes + wbytes) + queries.n_rows * wd * 4
+    score_kernel = int(round(post_bytes)) + queries.n_rows * wd * 4
     step = score_kernel + queries.n_rows * wd * 4  # the filter reads what was written
     return p_q, score_kernel, step
 
@@ -186,7 +190,8 @@ def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_
     total_ms = ev[0].elapsed_time(ev[steps])
     diag = batch.diagnostics()
     res = {"ids": ids.cpu().numpy(), "scores": sc.cpu().numpy(), "total_ms": total_ms, "step_ms": step_ms,
-           "timing": t, "diag": diag, "device_bytes": int(idx.info().device_bytes), "ws_bytes": ws.numel()}
+           "timing": t, "diag": diag, "device_bytes": int(idx.info().device_bytes), "ws_bytes": ws.numel(),
+           "dense_terms": idx.dense_terms()}
     if host_steps:
         # host CSR in (validation, per-query scales, upload), results copied back to host memory
         host_ms = []
@@ -420,8 +425,12 @@ def main():
             and args.k <= 1024 and n_tiles >= 16):
         # fused candidate filtering: score rows of the seed tiles (every 8th) only
         written = sum(min(tile_docs, n_docs - t * tile_docs) for t in range(0, n_tiles, 8))
-    p_q, score_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision],
-                                                   2 if args.kernel in ("tiled", "shared") else 4, written)
+    if args.kernel == "tiled" and args.precision != "u8":
+        idbytes = np.where(main_res["dense_terms"] != 0, 1.0 + 4.0 / 64.0, 2.0)
+    else:
+        idbytes = 2 if args.kernel in ("tiled", "shared") else 4
+    p_q, score_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision], idbytes,
+                                                     written)
     if args.kernel == "docpar":
         # document-parallel: every forward row (term id + fp32 weight) per query, plus one score write
         score_bytes = nq * (docs.nnz * 8 + n_docs * 4)

@@ -114,6 +114,9 @@ typedef struct gs_index_info_t {
     uint32_t flags;       /* gs_build_flags in effect */
     int32_t tile_grain;   /* doc-tile granularity of the segment table (docs) */
     int64_t n_tiles;      /* tiles of tile_grain docs covering the collection */
+    int64_t n_dense_terms; /* terms whose every 64-posting block spans at most 256 docs:
+                              the doc-tiled kernels read their doc ids as one byte per
+                              posting (distance to the block's first doc) */
 } gs_index_info_t;
 
 /* ------------------------------------------------------------------ misc -- */
@@ -141,7 +144,11 @@ const char* gs_last_error(void);
  *  - term_off[V+1] (int64) list starts, term_len[V] real lengths;
  *  - per 64-posting block: the largest weight and the first doc id;
  *  - per term and per tile of tile_grain docs: the offset of the first
- *    posting at or after the tile start (segment table for doc-tiled kernels).
+ *    posting at or after the tile start (segment table for doc-tiled kernels);
+ *  - doc ids again as 16-bit values (doc id modulo 65536), and, for the lists
+ *    whose every 64-posting block spans at most 256 docs ("dense" terms), as
+ *    one byte per posting: the distance to the block's first doc. The
+ *    doc-tiled kernels read 2 or 1 bytes per posting for the id instead of 4.
  * Synchronous: returns once the index is on the device.
  * Errors: GS_EINVAL (any check above, vocab_size < 1, n_docs < 0,
  *   n_docs >= 2^31, unknown precision or flag), GS_ENOMEM, GS_EHIP.
@@ -151,6 +158,16 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
                        uint32_t flags, void* hip_stream, gs_index* out);
 
 int32_t gs_index_info(gs_index index, gs_index_info_t* out);
+
+/*
+ * Byte-form flags of the index's terms (see n_dense_terms): out [vocab_size]
+ * (host, caller-owned) receives 1 for a term whose every 64-posting block spans at
+ * most 256 docs, else 0. For measurement: the doc-tiled kernels with fp32 or bf16
+ * weights read such a term's doc ids as 1 byte per posting plus one 4-byte block
+ * base per 64 postings. Errors: GS_EINVAL (null argument, vocab_size differs from
+ * the index's).
+ */
+int32_t gs_index_dense_terms(gs_index index, uint8_t* out, int32_t vocab_size);
 void gs_free_index(gs_index index);
 
 /*

@@ -61,7 +61,8 @@ class ServerStats(ctypes.Structure):
 class IndexInfo(ctypes.Structure):
     _fields_ = [("n_docs", ctypes.c_int64), ("nnz", ctypes.c_int64), ("padded_nnz", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("vocab_size", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("tile_grain", ctypes.c_int32), ("n_tiles", ctypes.c_int64)]
+                ("flags", ctypes.c_uint32), ("tile_grain", ctypes.c_int32), ("n_tiles", ctypes.c_int64),
+                ("n_dense_terms", ctypes.c_int64)]
 
 
 def _load() -> ctypes.CDLL:
@@ -78,6 +79,8 @@ def _load() -> ctypes.CDLL:
     lib.gs_build_index.restype = i32
     lib.gs_index_info.argtypes = [vp, P(IndexInfo)]
     lib.gs_index_info.restype = i32
+    lib.gs_index_dense_terms.argtypes = [vp, vp, i32]
+    lib.gs_index_dense_terms.restype = i32
     lib.gs_free_index.argtypes = [vp]
     lib.gs_free_index.restype = None
     lib.gs_layout_host.argtypes = [vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -196,6 +199,13 @@ class Index:
         i = IndexInfo()
         _check(lib.gs_index_info(self._h, ctypes.byref(i)), "gs_index_info")
         return i
+
+    def dense_terms(self) -> np.ndarray:
+        """uint8 [vocab]: 1 where the term's doc ids have the byte form (every 64-block spans <= 256 docs)."""
+        v = self.info().vocab_size
+        out = np.zeros(v, dtype=np.uint8)
+        _check(lib.gs_index_dense_terms(self._h, out.ctypes.data, v), "gs_index_dense_terms")
+        return out
 
     @property
     def n_docs(self) -> int:

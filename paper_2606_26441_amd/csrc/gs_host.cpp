@@ -295,6 +295,8 @@ int32_t build_layout(const Rows& r, int32_t vocab, int32_t precision, bool tiles
 struct gs_index_s {
     int device = 0;
     int64_t n_docs = 0, nnz = 0, padded = 0, n_grains = 0;
+    int64_t n_dense = 0;              // terms whose lists have the byte doc-id form
+    std::vector<uint8_t> term_dense;  // [V] host copy of the byte-form flags
     int32_t vocab = 0, precision = 0;
     uint32_t flags = 0;
     size_t bytes = 0;
@@ -639,8 +641,48 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     float* blk_max = nullptr;
     int32_t* blk_first = nullptr;
     if ((rc = dev_upload(ix->allocs, ix->bytes, L.blk_max.data(), L.blk_max.size(), &blk_max, s))) return done(rc);
-    if ((rc = dev_upload(ix->allocs, ix->bytes, L.blk_first.data(), L.blk_first.size(), &blk_first, s)))
+    if ((rc = dev_upload(ix->allocs, ix->bytes, L.blk_first.data(), L.blk_first.size(), &blk_first, s,
+                         kMaxChunk / kBlock)))
         return done(rc);
+    d.blk_first = blk_first;
+    {
+        // Byte form of the doc ids: a term whose every 64-posting block spans at most 256 docs
+        // stores each id as its distance to the block's first doc.
+        std::vector<uint8_t> dense, b8;
+        try {
+            dense.assign((size_t)vocab_size, 0);
+            b8.assign((size_t)L.padded, 0);
+        } catch (const std::bad_alloc&) {
+            return done(set_error(GS_ENOMEM, "host memory for the byte doc offsets"));
+        }
+        parallel_for(vocab_size, [&](int, int64_t a, int64_t b) {
+            for (int64_t v = a; v < b; v++) {
+                const int64_t o = L.term_off[(size_t)v];
+                const int64_t len = L.term_len[(size_t)v];
+                if (len == 0) continue;
+                bool ok = true;
+                for (int64_t k = 0; k < len && ok; k += kBlock) {
+                    const int64_t last = std::min(k + kBlock, len) - 1;
+                    ok = L.post_doc[(size_t)(o + last)] - L.post_doc[(size_t)(o + k)] <= 255;
+                }
+                if (!ok) continue;
+                dense[(size_t)v] = 1;
+                for (int64_t i = 0; i < len; i++)
+                    b8[(size_t)(o + i)] = (uint8_t)(L.post_doc[(size_t)(o + i)] - L.blk_first[(size_t)((o + i) / kBlock)]);
+            }
+        });
+        uint8_t *pd = nullptr, *pb = nullptr;
+        if ((rc = dev_upload(ix->allocs, ix->bytes, dense.data(), dense.size(), &pd, s))) return done(rc);
+        if ((rc = dev_upload(ix->allocs, ix->bytes, b8.data(), b8.size(), &pb, s, kPostSlack))) return done(rc);
+        d.term_dense = pd;
+        d.post_b8 = pb;
+        ix->n_dense = 0;
+        for (int32_t v = 0; v < vocab_size; v++) ix->n_dense += dense[(size_t)v];
+        ix->term_dense = dense;
+        // the uploads above are asynchronous: keep the host buffers until the stream is done
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return done(fail(GS_EHIP, std::string("upload: ") + hipGetErrorString(e)));
+    }
     if (flags & GS_KEEP_FORWARD) {
         int64_t* frp = nullptr;
         int32_t* ft = nullptr;
@@ -670,6 +712,15 @@ int32_t gs_index_info(gs_index ix, gs_index_info_t* out) {
     out->flags = ix->flags;
     out->tile_grain = 1 << kGrainShift;
     out->n_tiles = ix->n_grains;
+    out->n_dense_terms = ix->n_dense;
+    return GS_OK;
+}
+
+int32_t gs_index_dense_terms(gs_index ix, uint8_t* out, int32_t vocab_size) {
+    g_err.clear();
+    if (!ix || !out) return fail(GS_EINVAL, "null argument");
+    if (vocab_size != ix->vocab) return fail(GS_EINVAL, "vocab_size differs from the index's");
+    std::memcpy(out, ix->term_dense.data(), (size_t)ix->vocab);
     return GS_OK;
 }
 

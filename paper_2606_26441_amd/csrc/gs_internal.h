@@ -57,6 +57,12 @@ struct DevIndex {
     // size, lies inside one 65536-aligned range, so the doc-tiled kernels read 2 bytes per
     // posting for the id and recover the offset in the tile from the tile's base.
     const uint16_t* post_lo;
+    // Byte form of the doc ids of dense terms (every 64-posting block of the list spans at
+    // most 256 docs): post_b8[i] = doc(i) - blk_first[i / 64]. The doc-tiled kernels read
+    // these lists in whole blocks, 1 byte per posting for the id instead of 2.
+    const uint8_t* post_b8;    // [padded_nnz] (0 outside dense lists)
+    const int32_t* blk_first;  // [padded_nnz / 64] doc of each block's first posting (-1 if empty)
+    const uint8_t* term_dense; // [V] 1 if the term's list has the byte form
     const void* post_w;        // [padded_nnz] float | bf16 bits (uint16) | uint8
     const int32_t* tile_off;   // [V][n_grains+1] posting offset (relative to the list start)
     int64_t n_grains;          // ceil(n_docs / 8192)

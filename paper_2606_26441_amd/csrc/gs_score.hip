@@ -227,13 +227,19 @@ constexpr int acc_form() {
     return P == kFP32 ? kAccFx64 : (P == kBF16 ? kAccFx32 : kAccInt);
 }
 
+// Segments of a (query, tile) work item, dense terms first: a dense term's segment is
+// widened to whole 64-posting blocks (seg_edge = postings before | after the real
+// segment << 8), the others are exact.
 struct TileShared {
     int64_t seg_beg[kMaxQueryNnz];
     int32_t seg_len[kMaxQueryNnz];
     int32_t seg_cpre[kMaxQueryNnz + 1];
     double seg_qd[kMaxQueryNnz];   // w_q * 2^F (fixed point)
     uint32_t seg_q8[kMaxQueryNnz]; // uint8 query impact
+    uint16_t seg_edge[kMaxQueryNnz];
+    unsigned long long dmask[kMaxQueryNnz / kWave];  // dense terms per wavefront of the setup
 };
+static_assert(kMaxQueryNnz <= 512 && kMaxQueryNnz % kWave == 0, "segment setup: one thread per query term");
 
 // Chunk c of a tile's work (c is the same on every lane of the wavefront):
 // segment index, first posting and length, kept in scalar registers. The
@@ -241,7 +247,7 @@ struct TileShared {
 // search over the chunk prefix.
 template <bool TAB>
 __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* tab, int nq, int c, int ch, int* seg,
-                                         int64_t* p0, int* n) {
+                                         int64_t* p0, int* n, int* off_out) {
     int lo;
     if constexpr (TAB) {
         lo = tab[c];
@@ -254,7 +260,8 @@ __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* ta
         }
     }
     lo = __builtin_amdgcn_readfirstlane(lo);
-    const int off = (c - sh.seg_cpre[lo]) * ch;
+    const int off = __builtin_amdgcn_readfirstlane((c - sh.seg_cpre[lo]) * ch);
+    *off_out = off;
     *seg = lo;
     *n = __builtin_amdgcn_readfirstlane(min(ch, sh.seg_len[lo] - off));
     const int64_t p = sh.seg_beg[lo] + off;
@@ -264,8 +271,12 @@ __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* ta
 
 // Score one (query, doc tile) work item into LDS and flush it. Every thread of
 // the workgroup calls this; it ends after the flush (callers that loop must
-// synchronise before reusing the LDS).
-template <int P, int TS, int CH, bool RB>
+// synchronise before reusing the LDS). DB: read the byte doc ids of dense terms.
+// That saves HBM bytes but adds scalar work and a second chunk loop per item, so
+// it pays only where the kernel waits on HBM (the per-query kernel with fp32 or
+// bf16 weights), not where it is bound by instruction issue (shared traversal,
+// uint8 weights).
+template <int P, int TS, int CH, bool RB, bool DB>
 __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& qb, int32_t q0, int64_t tile, int ql,
                                            uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
                                            uint32_t* lds, TileShared& sh, int phase, SelState* state,
@@ -295,20 +306,54 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     const int nq = (int)(qb.q_row_ptr[q + 1] - qa);
     const int64_t g0 = tile << GPT;
     const int64_t g1 = min(g0 + (int64_t)(1 << GPT), ix.n_grains);
-    for (int t = tid; t < nq; t += BS) {
-        const int term = qb.q_term[qa + t];
+    // One thread per query term. Dense terms take the first segment slots (in query
+    // order), so their chunks come first and run in the byte-offset loop.
+    const int t = tid;
+    const bool live = t < nq;
+    int term = 0, a = 0, b = 0;
+    bool dense = false;
+    if (live) {
+        term = qb.q_term[qa + t];
         const int32_t* row = ix.tile_off + (int64_t)term * (ix.n_grains + 1);
-        const int a = row[g0], b = row[g1];
-        sh.seg_beg[t] = ix.term_off[term] + a;
+        a = row[g0];
+        b = row[g1];
+        dense = DB && ix.term_dense[term] != 0 && b > a;
+    }
+    if (t < kMaxQueryNnz) {
+        const unsigned long long m = __ballot(live && dense);
+        if (lane == 0) sh.dmask[wave] = m;
+    }
+    __syncthreads();
+    if (live) {
+        int before = 0, nd = 0;
+#pragma unroll
+        for (int w = 0; w < kMaxQueryNnz / kWave; w++) {
+            const int pc = __popcll(sh.dmask[w]);
+            nd += pc;
+            if (w < wave) before += pc;
+        }
+        before += __popcll(sh.dmask[wave] & ((1ull << lane) - 1ull));
+        const int slot = dense ? before : nd + (t - before);
         bool zero_weight;
         if constexpr (FX) {
-            sh.seg_qd[t] = qb.q_fx[qa + t];
-            zero_weight = !(sh.seg_qd[t] > 0.0);
+            const double qd = qb.q_fx[qa + t];
+            sh.seg_qd[slot] = qd;
+            zero_weight = !(qd > 0.0);
         } else {
-            sh.seg_q8[t] = (uint32_t)qb.q_w8[qa + t];
-            zero_weight = sh.seg_q8[t] == 0u;
+            const uint32_t q8 = (uint32_t)qb.q_w8[qa + t];
+            sh.seg_q8[slot] = q8;
+            zero_weight = q8 == 0u;
         }
-        sh.seg_len[t] = zero_weight ? 0 : b - a;  // a zero query weight adds nothing
+        int beg = a, len = b - a, edge = 0;
+        if (dense) {  // whole blocks: lists start 64-aligned and are padded to 64
+            beg = a & ~(kBlock - 1);
+            const int end = (b + kBlock - 1) & ~(kBlock - 1);
+            len = end - beg;
+            edge = (a - beg) | ((end - b) << 8);
+        }
+        sh.seg_beg[slot] = ix.term_off[term] + beg;
+        sh.seg_len[slot] = zero_weight ? 0 : len;  // a zero query weight adds nothing
+        sh.seg_edge[slot] = (uint16_t)edge;
     }
     __syncthreads();
     if (wave == 0) {
@@ -353,9 +398,10 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         __syncthreads();
     }
     struct Chunk {
-        uint32_t doc[U];  // doc id modulo 65536
+        uint32_t doc[U];  // doc id modulo 65536, or (dense) distance to the block's first doc
         uint32_t w[U];    // stored weight as fp32 bits, or the uint8 impact
-        int seg, n;
+        int32_t blk[U];   // (dense) first doc of the chunk's block u (scalar registers)
+        int seg, n, lo;   // postings [lo, n) of the chunk are the segment's (lo > 0: first slot only)
     };
     using WT = std::conditional_t<P == kU8, uint8_t, std::conditional_t<P == kBF16, uint16_t, uint32_t>>;
     // Loads are straight-line (no branch around them, so the compiler can wait for
@@ -364,71 +410,115 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // base is wave-uniform (scalar registers) and each lane's offset a clamped
     // 32-bit value, so no 64-bit address arithmetic is done per posting. The
     // chunk lookup is branch-free with the chunk table (an invalid slot looks up
-    // chunk 0 and gets length 0).
-    auto load = [&](auto use_tab, int c, Chunk& k, bool valid) {
+    // chunk 0 and gets length 0). A dense chunk covers whole blocks: it reads 1-byte
+    // distances, plus one block base per 64 postings.
+    auto load = [&](auto use_tab, auto dense_form, int c, Chunk& k, bool valid) {
+        constexpr bool DENSE = decltype(dense_form)::value;
         int64_t p0 = 0;
-        int n = 0;
-        chunk_at<decltype(use_tab)::value>(sh, tab, nq, valid ? c : 0, CH, &k.seg, &p0, &n);
-        k.n = valid ? n : 0;
-        const uint32_t last = (uint32_t)max(k.n - 1, 0);
-        const char* lb = reinterpret_cast<const char*>(ix.post_lo + p0);
+        int n = 0, off = 0;
+        chunk_at<decltype(use_tab)::value>(sh, tab, nq, valid ? c : 0, CH, &k.seg, &p0, &n, &off);
+        const uint32_t last = (uint32_t)max(n - 1, 0);
+        if constexpr (DENSE) {
+            const int edge = __builtin_amdgcn_readfirstlane((int)sh.seg_edge[k.seg]);
+            const int real_end = sh.seg_len[k.seg] - (edge >> 8) - off;
+            k.lo = off == 0 ? (edge & 0xFF) : 0;
+            k.n = valid ? min(n, real_end) : 0;
+            // wave-uniform: read through the constant address space, so the bases come by
+            // one scalar load per chunk (the array has slack for a chunk's worth of blocks)
+            using CI = const int32_t __attribute__((address_space(4)));
+            const CI* cb = (const CI*)(ix.blk_first + (p0 >> 6));
+#pragma unroll
+            for (int u = 0; u < U; u++) k.blk[u] = cb[u];
+        } else {
+            k.lo = 0;
+            k.n = valid ? n : 0;
+        }
+        const char* lb = DENSE ? reinterpret_cast<const char*>(ix.post_b8 + p0)
+                               : reinterpret_cast<const char*>(ix.post_lo + p0);
         const char* wb = reinterpret_cast<const char*>(reinterpret_cast<const WT*>(ix.post_w) + p0);
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const uint32_t off = min((uint32_t)(lane + u * kWave), last);
-            k.doc[u] = *reinterpret_cast<const uint16_t*>(lb + off * 2u);
-            const uint32_t wv = *reinterpret_cast<const WT*>(wb + off * (uint32_t)sizeof(WT));
+            const uint32_t off_u = min((uint32_t)(lane + u * kWave), last);
+            if constexpr (DENSE) k.doc[u] = *reinterpret_cast<const uint8_t*>(lb + off_u);
+            else k.doc[u] = *reinterpret_cast<const uint16_t*>(lb + off_u * 2u);
+            const uint32_t wv = *reinterpret_cast<const WT*>(wb + off_u * (uint32_t)sizeof(WT));
             k.w[u] = P == kBF16 ? wv << 16 : wv;
         }
     };
-    // accumulators indexed by doc id modulo 65536 (the tile's offset folded into the base)
+    // Accumulator of slot u: exact segments index by doc id modulo 65536 (the tile's offset
+    // folded into the base); dense ones by the distance plus the block's first doc relative
+    // to the tile (a scalar per slot).
     unsigned long long* acc64f = acc64 - lbase;
     uint32_t* acc32f = acc32 - lbase;
+    const int tbase = __builtin_amdgcn_readfirstlane((int)base);
     // A full chunk (every lane holds a posting in every slot) adds without the
-    // per-posting predicate; the last chunk of a segment is predicated.
-    auto apply = [&](const Chunk& k) {
+    // per-posting predicate; a segment's first (dense) and last chunks are predicated.
+    auto apply = [&](auto dense_form, const Chunk& k) {
+        constexpr bool DENSE = decltype(dense_form)::value;
+        // slot u's accumulator: the uniform part (block base) goes into the pointer, so each
+        // lane adds only its scaled offset
+        auto at = [&](auto* acc, int u) {
+            if constexpr (DENSE) return (acc + (k.blk[u] - tbase)) + k.doc[u];
+            else return acc + k.doc[u];
+        };
         auto add = [&](auto pred) {
             constexpr bool PRED = decltype(pred)::value;
+            auto ok = [&](int u) { return !PRED || ((u > 0 || lane >= k.lo) && lane + u * kWave < k.n); };
             if constexpr (AF == kAccFx64) {
+                unsigned long long* acc = DENSE ? acc64 : acc64f;
                 const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    if (!PRED || lane + u * kWave < k.n) atomicAdd(&acc64f[k.doc[u]], fx_prod<RB>(qd, k.w[u]));
+                    if (ok(u)) atomicAdd(at(acc, u), fx_prod<RB>(qd, k.w[u]));
             } else if constexpr (AF == kAccFx32) {
                 // the query's scale keeps every doc's sum below 2^32 units
+                uint32_t* acc = DENSE ? acc32 : acc32f;
                 const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    if (!PRED || lane + u * kWave < k.n)
-                        atomicAdd(&acc32f[k.doc[u]], (uint32_t)fx_prod<RB>(qd, k.w[u]));
+                    if (ok(u)) atomicAdd(at(acc, u), (uint32_t)fx_prod<RB>(qd, k.w[u]));
             } else {
+                uint32_t* acc = DENSE ? acc32 : acc32f;
                 const uint32_t q8v = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.seg_q8[k.seg]);
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    if (!PRED || lane + u * kWave < k.n) atomicAdd(&acc32f[k.doc[u]], q8v * k.w[u]);
+                    if (ok(u)) atomicAdd(at(acc, u), q8v * k.w[u]);
             }
         };
-        if (k.n == CH) add(std::false_type());
+        if (k.n == CH && k.lo == 0) add(std::false_type());
         else add(std::true_type());
     };
-    auto run = [&](auto use_tab) {
+    // Chunks c = wave, wave + NW, ... below `end`; returns the wavefront's first chunk at
+    // or past `end`.
+    auto run = [&](auto use_tab, auto dense_form, int c, int end) -> int {
         Chunk A, B;
-        int c = wave;
-        load(use_tab, c, A, c < total);
-        while (c < total) {
+        load(use_tab, dense_form, c, A, c < end);
+        while (c < end) {
             const int cb = c + NW;
-            load(use_tab, cb, B, cb < total);
-            apply(A);
-            if (cb >= total) break;
+            load(use_tab, dense_form, cb, B, cb < end);
+            apply(dense_form, A);
+            if (cb >= end) return cb;
             const int ca = cb + NW;
-            load(use_tab, ca, A, ca < total);
-            apply(B);
+            load(use_tab, dense_form, ca, A, ca < end);
+            apply(dense_form, B);
             c = ca;
         }
+        return c;
     };
     if (total > 0) {
-        if (tab) run(std::true_type());
-        else run(std::false_type());
+        int n_dense = 0;
+#pragma unroll
+        for (int w = 0; w < kMaxQueryNnz / kWave; w++) n_dense += __popcll(sh.dmask[w]);
+        const int total_d = __builtin_amdgcn_readfirstlane(sh.seg_cpre[n_dense]);
+        if (tab) {
+            int c = wave;
+            if constexpr (DB) c = total_d > 0 ? run(std::true_type(), std::true_type(), wave, total_d) : wave;
+            run(std::true_type(), std::false_type(), c, total);
+        } else {
+            int c = wave;
+            if constexpr (DB) c = total_d > 0 ? run(std::false_type(), std::true_type(), wave, total_d) : wave;
+            run(std::false_type(), std::false_type(), c, total);
+        }
     }
     __syncthreads();
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
@@ -458,14 +548,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ TileShared sh;
     const int64_t tile = phase_tile(phase, stride, (int64_t)blockIdx.x);
     if (phase != 3) {
-        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state, cand);
+        score_tile<P, TS, CH, RB, P != kU8>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state,
+                                             cand);
         return;
     }
     // rows of the queries that fell back from fused filtering (usually none): one
     // workgroup per tile walks the list
     const int nres = (int)counters[8];
     for (int r = 0; r < nres; r++) {
-        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, rescore_list[r], S, ld, hist1, lds, sh, phase, state, cand);
+        score_tile<P, TS, CH, RB, P != kU8>(ix, qb, q0, tile, rescore_list[r], S, ld, hist1, lds, sh, phase, state,
+                                             cand);
         __syncthreads();
     }
 }
@@ -498,7 +590,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (item >= items) break;
         const int64_t tile = phase_tile(phase, stride, x + 8 * (item / nq));
         const int ql = phase == 3 ? rescore_list[item % nq] : order[item % nq];
-        score_tile<P, TS, CH, RB>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh, phase, state, cand);
+        score_tile<P, TS, CH, RB, false>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh, phase, state, cand);
         __syncthreads();
     }
 }
