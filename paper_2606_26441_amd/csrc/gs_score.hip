@@ -227,6 +227,11 @@ constexpr int acc_form() {
     return P == kFP32 ? kAccFx64 : (P == kBF16 ? kAccFx32 : kAccInt);
 }
 
+// Word 3 of a raw buffer descriptor on the gfx9 family (gfx950 included): no stride,
+// no swizzle, 32-bit data format; the hardware range-checks each lane's byte offset
+// against the record count and returns 0 past it.
+constexpr int kRawBufferWord3 = 0x00020000;
+
 // Segments of a (query, tile) work item, dense terms first: a dense term's segment is
 // widened to whole 64-posting blocks (seg_edge = postings before | after the real
 // segment << 8), the others are exact.
@@ -400,16 +405,15 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     struct Chunk {
         uint32_t doc[U];  // doc id modulo 65536, or (dense) distance to the block's first doc
         uint32_t w[U];    // stored weight as fp32 bits, or the uint8 impact
-        int32_t blk[U];   // (dense) first doc of the chunk's block u (scalar registers)
+        int32_t blk;      // (dense) lane u < U: first doc of the chunk's block u
         int seg, n, lo;   // postings [lo, n) of the chunk are the segment's (lo > 0: first slot only)
     };
     using WT = std::conditional_t<P == kU8, uint8_t, std::conditional_t<P == kBF16, uint16_t, uint32_t>>;
     // Loads are straight-line (no branch around them, so the compiler can wait for
-    // the older chunk only): lanes past the end of a chunk re-read its last posting,
-    // and an empty slot reads posting 0 (the arrays are never empty). The chunk's
-    // base is wave-uniform (scalar registers) and each lane's offset a clamped
-    // 32-bit value, so no 64-bit address arithmetic is done per posting. The
-    // chunk lookup is branch-free with the chunk table (an invalid slot looks up
+    // the older chunk only): lanes past the end of a chunk read 0, and an empty slot
+    // reads nothing (record count 0). The chunk's base is wave-uniform (a buffer
+    // descriptor in scalar registers), so no address arithmetic is done per posting.
+    // The chunk lookup is branch-free with the chunk table (an invalid slot looks up
     // chunk 0 and gets length 0). A dense chunk covers whole blocks: it reads 1-byte
     // distances, plus one block base per 64 postings.
     auto load = [&](auto use_tab, auto dense_form, int c, Chunk& k, bool valid) {
@@ -417,31 +421,43 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         int64_t p0 = 0;
         int n = 0, off = 0;
         chunk_at<decltype(use_tab)::value>(sh, tab, nq, valid ? c : 0, CH, &k.seg, &p0, &n, &off);
-        const uint32_t last = (uint32_t)max(n - 1, 0);
         if constexpr (DENSE) {
             const int edge = __builtin_amdgcn_readfirstlane((int)sh.seg_edge[k.seg]);
             const int real_end = sh.seg_len[k.seg] - (edge >> 8) - off;
             k.lo = off == 0 ? (edge & 0xFF) : 0;
             k.n = valid ? min(n, real_end) : 0;
-            // wave-uniform: read through the constant address space, so the bases come by
-            // one scalar load per chunk (the array has slack for a chunk's worth of blocks)
-            using CI = const int32_t __attribute__((address_space(4)));
-            const CI* cb = (const CI*)(ix.blk_first + (p0 >> 6));
-#pragma unroll
-            for (int u = 0; u < U; u++) k.blk[u] = cb[u];
+            // one register for the chunk's block bases (lane u holds block u); a slot takes
+            // its base with a lane read, which keeps scalar registers free
+            const int nblk = (n + kBlock - 1) >> 6;
+            k.blk = ix.blk_first[(p0 >> 6) + min(lane, max(nblk - 1, 0))];
         } else {
             k.lo = 0;
             k.n = valid ? n : 0;
         }
-        const char* lb = DENSE ? reinterpret_cast<const char*>(ix.post_b8 + p0)
-                               : reinterpret_cast<const char*>(ix.post_lo + p0);
-        const char* wb = reinterpret_cast<const char*>(reinterpret_cast<const WT*>(ix.post_w) + p0);
+        // Buffer loads over the chunk: the descriptor's record count is the chunk's bytes,
+        // so lanes past its end read 0 without a clamp, and slot u's offset is the
+        // instruction's immediate (lane offsets are one register for the whole loop).
+        const int nrec = valid ? n : 0;
+        const void* lb = DENSE ? static_cast<const void*>(ix.post_b8 + p0) : static_cast<const void*>(ix.post_lo + p0);
+        const void* wb = static_cast<const void*>(reinterpret_cast<const WT*>(ix.post_w) + p0);
+        const __amdgpu_buffer_rsrc_t rid =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(lb), (short)0, nrec * (DENSE ? 1 : 2), kRawBufferWord3);
+        const __amdgpu_buffer_rsrc_t rw =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(wb), (short)0, nrec * (int)sizeof(WT), kRawBufferWord3);
+        // z is 0 (posting offsets stay far below 2^48) but not a loop invariant, so the
+        // compiler keeps one lane offset per chunk and each slot's offset in the
+        // instruction, instead of holding a register per slot across the loop.
+        const int z = (int)((uint64_t)p0 >> 48);
+        const int vid = (lane << (DENSE ? 0 : 1)) + z;
+        const int vw = lane * (int)sizeof(WT) + z;
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const uint32_t off_u = min((uint32_t)(lane + u * kWave), last);
-            if constexpr (DENSE) k.doc[u] = *reinterpret_cast<const uint8_t*>(lb + off_u);
-            else k.doc[u] = *reinterpret_cast<const uint16_t*>(lb + off_u * 2u);
-            const uint32_t wv = *reinterpret_cast<const WT*>(wb + off_u * (uint32_t)sizeof(WT));
+            if constexpr (DENSE) k.doc[u] = __builtin_amdgcn_raw_buffer_load_b8(rid, vid + u * kWave, 0, 0);
+            else k.doc[u] = __builtin_amdgcn_raw_buffer_load_b16(rid, vid + u * kWave * 2, 0, 0);
+            uint32_t wv;
+            if constexpr (sizeof(WT) == 4) wv = __builtin_amdgcn_raw_buffer_load_b32(rw, vw + u * kWave * 4, 0, 0);
+            else if constexpr (sizeof(WT) == 2) wv = __builtin_amdgcn_raw_buffer_load_b16(rw, vw + u * kWave * 2, 0, 0);
+            else wv = __builtin_amdgcn_raw_buffer_load_b8(rw, vw + u * kWave, 0, 0);
             k.w[u] = P == kBF16 ? wv << 16 : wv;
         }
     };
@@ -458,7 +474,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         // slot u's accumulator: the uniform part (block base) goes into the pointer, so each
         // lane adds only its scaled offset
         auto at = [&](auto* acc, int u) {
-            if constexpr (DENSE) return (acc + (k.blk[u] - tbase)) + k.doc[u];
+            if constexpr (DENSE) return (acc + (__builtin_amdgcn_readlane(k.blk, u) - tbase)) + k.doc[u];
             else return acc + k.doc[u];
         };
         auto add = [&](auto pred) {
