@@ -25,7 +25,9 @@
 // Weight forms of the doc-tiled kernels: fp32 (products rounded to units of a
 // per-query scale and summed exactly in 64-bit fixed point), bf16 (stored as the
 // upper 16 bits of the fp32 pattern; 32-bit fixed point, then fp64 rescoring of
-// the candidates) and uint8 impacts (int32 products and sums, exact). With fused
+// the candidates) and uint8 impacts (int32 products and sums, exact). Doc ids are
+// read as 16-bit offsets, or, for dense terms in k_score_tiled with fp32 and bf16
+// weights, as one byte per posting from the 64-block's first doc. With fused
 // candidate filtering a search runs them in phases: the seed tiles, then the
 // other tiles appending candidates at or above a bound while they flush, then a
 // pass that writes the rows of the queries that fell back (see gs_topk.hip).
