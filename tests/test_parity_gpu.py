@@ -387,6 +387,8 @@ def test_byte_doc_ids_of_dense_terms(precision):
             idx = gs.Index.from_rows(docs, precision)
             assert np.array_equal(idx.dense_terms(), expect_dense)
             assert idx.info().n_dense_terms == int(expect_dense.sum())
+            short = np.zeros(docs.vocab - 1, dtype=np.uint8)
+            assert gs.lib.gs_index_dense_terms(idx.handle, short.ctypes.data, docs.vocab - 1) == -1
             idx.close()
             ids, sc, _ = _run(gs, docs, qs, k, precision, kernel, tile_docs=tile_docs, chunk=chunk)
             for q in range(qs.n_rows):
