@@ -438,7 +438,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         }
         // Buffer loads over the chunk: the descriptor's record count is the chunk's bytes,
         // so lanes past its end read 0 without a clamp, and slot u's offset is the
-        // instruction's immediate (lane offsets are one register for the whole loop).
+        // instruction's immediate (one lane-offset register per chunk).
         const int nrec = valid ? n : 0;
         const void* lb = DENSE ? static_cast<const void*>(ix.post_b8 + p0) : static_cast<const void*>(ix.post_lo + p0);
         const void* wb = static_cast<const void*>(reinterpret_cast<const WT*>(ix.post_w) + p0);
