@@ -178,13 +178,17 @@ void gs_free_index(gs_index index);
  *   term_off [vocab_size+1] int64, term_len [vocab_size] int32,
  *   post_doc [padded_nnz] int32, post_w [padded_nnz] float (the stored weight
  *   converted back to float: fp32 as is, bf16 widened, uint8 as its integer),
- *   blk_max [padded_nnz/64] float, blk_first_doc [padded_nnz/64] int32.
- * Errors as gs_build_index.
+ *   blk_max [padded_nnz/64] float, blk_first_doc [padded_nnz/64] int32,
+ *   term_dense [vocab_size] uint8 (1 for a term whose every 64-posting block
+ *   spans at most 256 docs), post_b8 [padded_nnz] uint8 (for those terms' real
+ *   postings: doc id minus the block's first doc id; 0 elsewhere).
+ * Any array may be NULL. Errors as gs_build_index.
  */
 int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* term_ids,
                        const float* weights, int64_t nnz, int32_t vocab_size, int32_t precision,
                        int64_t* out_padded_nnz, int64_t* term_off, int32_t* term_len,
-                       int32_t* post_doc, float* post_w, float* blk_max, int32_t* blk_first_doc);
+                       int32_t* post_doc, float* post_w, float* blk_max, int32_t* blk_first_doc,
+                       uint8_t* term_dense, uint8_t* post_b8);
 
 /* --------------------------------------------------------- query batches -- */
 

@@ -83,7 +83,7 @@ def _load() -> ctypes.CDLL:
     lib.gs_index_dense_terms.restype = i32
     lib.gs_free_index.argtypes = [vp]
     lib.gs_free_index.restype = None
-    lib.gs_layout_host.argtypes = [vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.gs_layout_host.argtypes = [vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.gs_layout_host.restype = i32
     lib.gs_batch_create.argtypes = [vp, vp, i32, vp, vp, i64, vp, i32, vp, P(vp)]
     lib.gs_batch_create.restype = i32
@@ -161,15 +161,18 @@ def layout_host(row_ptr, terms, weights, vocab: int, precision="fp32"):
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     padded = ctypes.c_int64(0)
     _check(lib.gs_layout_host(rp.ctypes.data, n, t.ctypes.data, w.ctypes.data, t.shape[0], vocab, prec,
-                              ctypes.addressof(padded), None, None, None, None, None, None), "gs_layout_host")
+                              ctypes.addressof(padded), None, None, None, None, None, None, None, None),
+           "gs_layout_host")
     P = padded.value
     out = dict(term_off=np.empty(vocab + 1, np.int64), term_len=np.empty(vocab, np.int32),
                post_doc=np.empty(P, np.int32), post_w=np.empty(P, np.float32),
-               blk_max=np.empty(P // 64, np.float32), blk_first_doc=np.empty(P // 64, np.int32))
+               blk_max=np.empty(P // 64, np.float32), blk_first_doc=np.empty(P // 64, np.int32),
+               term_dense=np.empty(vocab, np.uint8), post_b8=np.empty(P, np.uint8))
     _check(lib.gs_layout_host(rp.ctypes.data, n, t.ctypes.data, w.ctypes.data, t.shape[0], vocab, prec,
                               ctypes.addressof(padded), out["term_off"].ctypes.data, out["term_len"].ctypes.data,
                               out["post_doc"].ctypes.data, out["post_w"].ctypes.data, out["blk_max"].ctypes.data,
-                              out["blk_first_doc"].ctypes.data), "gs_layout_host")
+                              out["blk_first_doc"].ctypes.data, out["term_dense"].ctypes.data,
+                              out["post_b8"].ctypes.data), "gs_layout_host")
     return out
 
 

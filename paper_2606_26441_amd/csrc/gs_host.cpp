@@ -288,6 +288,29 @@ int32_t build_layout(const Rows& r, int32_t vocab, int32_t precision, bool tiles
     return GS_OK;
 }
 
+// Byte form of the doc ids: a term whose every 64-posting block spans at most 256 docs
+// ("dense") also stores each id as its distance to the block's first doc.
+void byte_form(const Layout& L, std::vector<uint8_t>& dense, std::vector<uint8_t>& b8) {
+    dense.assign((size_t)L.vocab, 0);
+    b8.assign((size_t)L.padded, 0);
+    parallel_for(L.vocab, [&](int, int64_t a, int64_t b) {
+        for (int64_t v = a; v < b; v++) {
+            const int64_t o = L.term_off[(size_t)v];
+            const int64_t len = L.term_len[(size_t)v];
+            if (len == 0) continue;
+            bool ok = true;
+            for (int64_t k = 0; k < len && ok; k += kBlock) {
+                const int64_t last = std::min(k + kBlock, len) - 1;
+                ok = L.post_doc[(size_t)(o + last)] - L.post_doc[(size_t)(o + k)] <= 255;
+            }
+            if (!ok) continue;
+            dense[(size_t)v] = 1;
+            for (int64_t i = 0; i < len; i++)
+                b8[(size_t)(o + i)] = (uint8_t)(L.post_doc[(size_t)(o + i)] - L.blk_first[(size_t)((o + i) / kBlock)]);
+        }
+    });
+}
+
 }  // namespace
 
 // ===================================================================== API ==
@@ -512,7 +535,8 @@ const char* gs_last_error(void) { return g_err.c_str(); }
 
 int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* term_ids, const float* weights,
                        int64_t nnz, int32_t vocab_size, int32_t precision, int64_t* out_padded_nnz, int64_t* term_off,
-                       int32_t* term_len, int32_t* post_doc, float* post_w, float* blk_max, int32_t* blk_first_doc) {
+                       int32_t* term_len, int32_t* post_doc, float* post_w, float* blk_max, int32_t* blk_first_doc,
+                       uint8_t* term_dense, uint8_t* post_b8) {
     g_err.clear();
     if (vocab_size < 1) return fail(GS_EINVAL, "vocab_size < 1");
     if (precision < kFP32 || precision > kU8) return fail(GS_EINVAL, "unknown precision");
@@ -521,7 +545,8 @@ int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     int32_t rc = check_rows(r, nnz, vocab_size, vocab_size, "documents");
     if (rc != GS_OK) return rc;
     Layout L;
-    const bool want_arrays = term_off || term_len || post_doc || post_w || blk_max || blk_first_doc;
+    const bool want_arrays =
+        term_off || term_len || post_doc || post_w || blk_max || blk_first_doc || term_dense || post_b8;
     if (!want_arrays) {
         if (!out_padded_nnz) return fail(GS_EINVAL, "nothing requested");
         sizes_only(r, vocab_size, L);
@@ -538,6 +563,16 @@ int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
         for (int64_t i = 0; i < L.padded; i++) post_w[i] = stored_weight(L, i);
     if (blk_max) std::memcpy(blk_max, L.blk_max.data(), L.blk_max.size() * 4);
     if (blk_first_doc) std::memcpy(blk_first_doc, L.blk_first.data(), L.blk_first.size() * 4);
+    if (term_dense || post_b8) {
+        std::vector<uint8_t> dense, b8;
+        try {
+            byte_form(L, dense, b8);
+        } catch (const std::bad_alloc&) {
+            return fail(GS_ENOMEM, "host memory for the byte doc offsets");
+        }
+        if (term_dense) std::memcpy(term_dense, dense.data(), dense.size());
+        if (post_b8) std::memcpy(post_b8, b8.data(), b8.size());
+    }
     return GS_OK;
 }
 
@@ -650,27 +685,10 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
         // stores each id as its distance to the block's first doc.
         std::vector<uint8_t> dense, b8;
         try {
-            dense.assign((size_t)vocab_size, 0);
-            b8.assign((size_t)L.padded, 0);
+            byte_form(L, dense, b8);
         } catch (const std::bad_alloc&) {
             return done(set_error(GS_ENOMEM, "host memory for the byte doc offsets"));
         }
-        parallel_for(vocab_size, [&](int, int64_t a, int64_t b) {
-            for (int64_t v = a; v < b; v++) {
-                const int64_t o = L.term_off[(size_t)v];
-                const int64_t len = L.term_len[(size_t)v];
-                if (len == 0) continue;
-                bool ok = true;
-                for (int64_t k = 0; k < len && ok; k += kBlock) {
-                    const int64_t last = std::min(k + kBlock, len) - 1;
-                    ok = L.post_doc[(size_t)(o + last)] - L.post_doc[(size_t)(o + k)] <= 255;
-                }
-                if (!ok) continue;
-                dense[(size_t)v] = 1;
-                for (int64_t i = 0; i < len; i++)
-                    b8[(size_t)(o + i)] = (uint8_t)(L.post_doc[(size_t)(o + i)] - L.blk_first[(size_t)((o + i) / kBlock)]);
-            }
-        });
         uint8_t *pd = nullptr, *pb = nullptr;
         if ((rc = dev_upload(ix->allocs, ix->bytes, dense.data(), dense.size(), &pd, s))) return done(rc);
         if ((rc = dev_upload(ix->allocs, ix->bytes, b8.data(), b8.size(), &pb, s, kPostSlack))) return done(rc);

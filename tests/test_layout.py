@@ -71,3 +71,32 @@ def test_empty_rows_and_unused_terms():
     assert L["term_len"].tolist() == [0, 0, 0, 2, 0, 1, 0, 0]
     assert L["term_off"].tolist() == [0, 0, 0, 0, 64, 64, 128, 128, 128]
     assert L["post_doc"][:3].tolist() == [1, 3, -1] and L["post_doc"][64] == 1
+
+
+def test_byte_form_of_dense_terms():
+    # The byte form must rebuild every doc id of a dense term from its block's first doc, and
+    # the dense flags must match a classification done here from the rows themselves.
+    import paper_2606_26441_amd as gs
+    from helpers import dense_terms, mixed_density_collection
+    docs = mixed_density_collection(np.random.default_rng(77))
+    L = gs.layout_host(docs.row_ptr, docs.terms, docs.weights, docs.vocab, "fp32")
+    expect = dense_terms(docs)
+    assert list(np.flatnonzero(expect)) == [0, 1, 2, 6]
+    assert np.array_equal(L["term_dense"], expect)
+    P = L["post_doc"].shape[0]
+    real = np.zeros(P, dtype=bool)
+    in_dense = np.zeros(P, dtype=bool)
+    for v in range(docs.vocab):
+        a, n = int(L["term_off"][v]), int(L["term_len"][v])
+        real[a:a + n] = True
+        in_dense[a:a + n] = bool(expect[v])
+    base = np.repeat(L["blk_first_doc"], 64)
+    rebuilt = base[in_dense] + L["post_b8"][in_dense].astype(np.int64)
+    assert np.array_equal(rebuilt, L["post_doc"][in_dense])
+    assert not L["post_b8"][~in_dense].any()
+    # the flagged terms are exactly those whose blocks stay within 256 docs
+    for v in np.flatnonzero(expect):
+        a, n = int(L["term_off"][v]), int(L["term_len"][v])
+        d = L["post_doc"][a:a + n]
+        spans = [d[k:k + 64][-1] - d[k] for k in range(0, n, 64)]
+        assert max(spans) <= 255

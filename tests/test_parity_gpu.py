@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import workload
-from helpers import csr, dyadic, random_rows
+from helpers import csr, dense_terms, dyadic, mixed_density_collection, random_rows
 from parity_rules import check_batch, check_exact_f64, check_exact_int
 
 pytestmark = pytest.mark.gpu
@@ -319,45 +319,6 @@ def test_bf16_fixed_point_headroom(kernel):
         check_exact_f64(ids[q], sc[q], rid[q], rsc[q], "headroom q%d" % q)
 
 
-def _dense_terms(docs):
-    """uint8 [vocab]: 1 for terms whose doc-sorted list has every 64-posting block spanning at most 256 docs."""
-    doc_of = np.repeat(np.arange(docs.n_rows), np.diff(docs.row_ptr))
-    order = np.lexsort((doc_of, docs.terms))
-    t_sorted, d_sorted = docs.terms[order], doc_of[order]
-    starts = np.flatnonzero(np.r_[True, t_sorted[1:] != t_sorted[:-1]])
-    ends = np.r_[starts[1:], len(t_sorted)]
-    out = np.zeros(docs.vocab, dtype=np.uint8)
-    for a, b in zip(starts, ends):
-        ids = d_sorted[a:b]
-        first = ids[0::64]
-        last = ids[np.minimum(np.arange(0, b - a, 64) + 63, b - a - 1)]
-        out[t_sorted[a]] = int(np.all(last - first <= 255))
-    return out
-
-
-def _mixed_density_collection(rng, n_docs=53_251, vocab=320):
-    # term 0: every doc; 1: every 3rd; 2: every 4th (blocks span 252 docs): byte form.
-    # 3: every 5th; 4: every doc but a 300-doc hole; 5: every 2nd doc, then every 7th: 2-byte form.
-    # 6: ten docs around the 8192 boundary (one block across two tiles, byte form);
-    # 7: two clusters far apart in one block (2-byte form); 10.. : sparse random terms.
-    d = np.arange(n_docs)
-    members = {0: d, 1: d[d % 3 == 0], 2: d[d % 4 == 1], 3: d[d % 5 == 2],
-               4: d[(d < 20_000) | (d >= 20_300)], 5: np.r_[d[(d < 30_000) & (d % 2 == 0)], d[(d >= 30_000) & (d % 7 == 0)]],
-               6: np.arange(8190, 8200), 7: np.r_[np.arange(16_380, 16_390), np.arange(40_000, 40_003)]}
-    rows = [[] for _ in range(n_docs)]
-    for t, ds in members.items():
-        for x in ds:
-            rows[x].append(t)
-    for x in range(n_docs):
-        extra = rng.choice(np.arange(10, vocab), size=int(rng.integers(0, 6)), replace=False)
-        rows[x].extend(int(e) for e in extra)
-    out = []
-    for r in rows:
-        w = dyadic(rng, len(r))
-        out.append(sorted(zip(r, w.tolist())))
-    return csr(out, vocab)
-
-
 @pytest.mark.parametrize("precision", ["fp32", "u8", "bf16"])
 def test_byte_doc_ids_of_dense_terms(precision):
     # dense and 2-byte lists mixed in one query, segments that start and end inside a
@@ -366,7 +327,7 @@ def test_byte_doc_ids_of_dense_terms(precision):
     # check the same instances on the 2-byte form)
     gs = _gs()
     rng = np.random.default_rng(77)
-    docs = _mixed_density_collection(rng)
+    docs = mixed_density_collection(rng)
     qrows = [[(0, 1.0), (1, 0.5), (2, 2.0)], [(3, 1.0), (4, 0.25), (5, 1.5)],
              [(t, float(dyadic(rng, 1)[0])) for t in range(8)] + [(11, 1.0), (200, 0.5)],
              [(6, 3.0)], [(0, 0.0), (3, 1.0)], [(6, 1.0), (7, 1.0)]]
@@ -379,7 +340,7 @@ def test_byte_doc_ids_of_dense_terms(precision):
         rid, rsc = oracle.topk_i64(docs, qs, k)
     else:
         rid, rsc = oracle.topk_f64(docs, qs, k)
-    expect_dense = _dense_terms(docs)
+    expect_dense = dense_terms(docs)
     assert list(np.flatnonzero(expect_dense)) == [0, 1, 2, 6]
     shapes = [(8192, 64), (16384, 1024)] + ([(32768, 256)] if precision != "fp32" else [(8192, 256)])
     for kernel in ("tiled", "shared"):
