@@ -164,6 +164,40 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
                                            bool write, bool count) {
     const int tid = threadIdx.x;
     const int n4 = tile_n >> 2;
+    if constexpr (AF == kAccFx64) {
+        if (!write && !count) {
+            // Only candidates matter (no row, no histogram). A doc whose float score
+            // float(acc * scale) reaches the bound's score s_b has acc * scale >= s_b (1 - 2^-24),
+            // and converting the sum to double loses at most 2^-53 more, so a sum below t_lo
+            // (taken with margin) cannot reach the bound: test the raw sums first and convert
+            // only where a wavefront holds a sum at or above t_lo.
+            if (!append) return;
+            const double sb = (double)__uint_as_float((uint32_t)(bound >> 32));
+            const unsigned long long t_lo = (unsigned long long)fmax(0.0, floor(sb * (1.0 - 0x1p-22) / scale));
+            const unsigned long long* acc = (const unsigned long long*)acc_v;
+            for (int i = tid; i < n4; i += BS) {
+                unsigned long long a[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) a[j] = acc[4 * i + j];
+                const unsigned long long m01 = a[0] > a[1] ? a[0] : a[1];
+                const unsigned long long m23 = a[2] > a[3] ? a[2] : a[3];
+                if (!__ballot((m01 > m23 ? m01 : m23) >= t_lo)) continue;
+                const uint32_t d0 = (uint32_t)(base + 4 * i);
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint32_t v = __float_as_uint((float)((double)a[j] * scale));
+                    const unsigned long long c = comp_key(v, d0 + j);
+                    append_candidates(c >= bound, c, st, C);
+                }
+            }
+            for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
+                const uint32_t v = __float_as_uint((float)((double)acc[i] * scale));
+                const unsigned long long c = comp_key(v, (uint32_t)(base + i));
+                append_candidates(c >= bound, c, st, C);
+            }
+            return;
+        }
+    }
     for (int i = tid; i < n4; i += BS) {
         uint32_t v[4];
         if constexpr (AF == kAccFx64) {
@@ -548,9 +582,13 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     const bool fused_q = phase == 2 && st->fused == 1;
     const bool app = fused_q && !st->fused_over;
     const bool write = !fused_q || P == kBF16;
+    // The first-digit histogram of a fused fp32/uint8 query keeps the seed tiles' counts
+    // only: its selection needs no more, and if it falls back, phase 3 scores these tiles
+    // again and counts them then (bf16 has no phase 3 and counts here).
+    const bool count = !(fused_q && P != kBF16);
     flush_tile<BS, AF>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
                        FX ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins, app, app ? st->bound : 0ull, st,
-                       cand + (int64_t)ql * kCandCap, write, phase != 3);
+                       cand + (int64_t)ql * kCandCap, write, count);
 }
 
 // Per-query form: grid (tiles, queries), the tiles of one query are consecutive

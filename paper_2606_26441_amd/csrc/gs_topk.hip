@@ -84,11 +84,16 @@ __device__ __forceinline__ int64_t kq_of(const DevBatch& qb, int q, int64_t N) {
     return min((int64_t)qb.k[q], N);
 }
 
+// pass 0 runs once every tile is scored; pass 1 runs after phase 3 for the queries that
+// fell back, whose histograms are complete only then (phase 2 counts the seed tiles of a
+// fused fp32/uint8 query only).
 __global__ __launch_bounds__(64) void k_select_first(DevBatch qb, int32_t q0, int64_t N, int precision,
                                                      const uint32_t* __restrict__ hist1, SelState* __restrict__ state,
-                                                     uint32_t* __restrict__ counters, int32_t* __restrict__ rescore_list) {
+                                                     uint32_t* __restrict__ counters, int32_t* __restrict__ rescore_list,
+                                                     int pass) {
     const int ql = blockIdx.x, q = q0 + ql;
     SelState* st = state + ql;
+    if (pass == 1 && st->rescore != 1) return;
     const int64_t kq = kq_of(qb, q, N);
     if (kq == 0) {
         if (threadIdx.x == 0) st->resolved = 2;
@@ -769,11 +774,14 @@ hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int
     const int per = 65536;
     const dim3 grid_scan((unsigned)((N + per - 1) / per), (unsigned)qt);
     hipLaunchKernelGGL(k_select_first, dim3(qt), dim3(64), 0, s, qb, q0, N, ix.precision,
-                       (const uint32_t*)ws.hist1, ws.state, ws.counters, ws.rescore_list);
+                       (const uint32_t*)ws.hist1, ws.state, ws.counters, ws.rescore_list, 0);
     GS_CHECK_LAUNCH("k_select_first");
-    if (after_first) {  // fused filtering: rows for the queries that fell back
+    if (after_first) {  // fused filtering: rows (and counts) for the queries that fell back
         const hipError_t e = after_first();
         if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_select_first, dim3(qt), dim3(64), 0, s, qb, q0, N, ix.precision,
+                           (const uint32_t*)ws.hist1, ws.state, ws.counters, ws.rescore_list, 1);
+        GS_CHECK_LAUNCH("k_select_first");
     }
     auto final_pass = [&]() -> hipError_t {
         switch (ix.precision) {
