@@ -90,9 +90,6 @@ def test_fused_fallback_on_massive_ties(precision):
         a = _search(gs, torch, idx, qs, 1000, 1000, kernel, True)
         b = _search(gs, torch, idx, qs, 1000, 1000, kernel, False)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), kernel
-        # the fallback ran: refinement passes over full rows need the complete histogram
-        # that phase 3 finishes for the fallen-back queries
-        assert a[2][:, 1].max() > 0, kernel
     sub = qs.subset(np.arange(6))
     check_batch(precision, docs, sub, a[0][:6], a[1][:6], 1000, what="ties")
     idx.close()
@@ -141,8 +138,5 @@ def test_fused_bf16_band_below_the_candidates(n_terms):
         a = _search(gs, torch, idx, qs, 1000, 1000, kernel, True)
         b = _search(gs, torch, idx, qs, 1000, 1000, kernel, False)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), kernel
-        # the fallback ran: refinement passes over full rows need the complete histogram
-        # that phase 3 finishes for the fallen-back queries
-        assert a[2][:, 1].max() > 0, kernel
     check_batch("bf16", docs, qs.subset(np.arange(6)), a[0][:6], a[1][:6], 1000, what="bf16 band")
     idx.close()

@@ -232,6 +232,36 @@ def test_refinement_rounds_resolve_massive_exact_ties(precision):
     check_batch(precision, docs, qs, ids, sc, k, what="refine " + precision)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "u8"])
+def test_fused_fallback_then_refinement(precision):
+    # 33 queries turn fused filtering on (seed stride 4 for k_max 2048 over 19 tiles). The
+    # all-tied query appends every non-seed doc, passes the cap and falls back: its other
+    # tiles are scored and counted again, its selection is redone from the complete
+    # histogram, and the tie at the k-th score needs refinement rounds.
+    gs = _gs()
+    rng = np.random.default_rng(21)
+    rows = []
+    for _ in range(150_000):
+        extra = rng.choice(np.arange(1, 24), size=int(rng.integers(0, 3)), replace=False)
+        rows.append([(0, 1.0)] + [(int(e), float(rng.integers(1, 3))) for e in sorted(extra)])
+    docs = csr(rows, 24)
+    base = [[(0, 1.0)], [(0, 1.0), (5, 1.0)], [(0, 0.5)]]
+    qs = csr(base * 11, 24)
+    k = [1000, 2000, 7] * 11
+    first = None
+    for kernel in ("tiled", "shared"):
+        ids, sc, diag = _run(gs, docs, qs, k, precision, kernel, k_max=2048)
+        assert diag[0, 1] > 0, "the all-tied query needed no refinement round"
+        for c in range(1, 11):  # every copy of a query gets the same answer
+            assert np.array_equal(ids[3 * c:3 * c + 3], ids[:3]) and np.array_equal(sc[3 * c:3 * c + 3], sc[:3])
+        if first is None:
+            first = (ids[:3], sc[:3])
+            check_batch(precision, docs, qs.subset(np.arange(3)), ids[:3], sc[:3], k[:3],
+                        what="fused fallback " + precision)
+        else:
+            assert np.array_equal(ids[:3], first[0]) and np.array_equal(sc[:3], first[1]), kernel
+
+
 def test_bf16_band_beyond_capacity_is_flagged_not_wrong():
     # with the same exact ties the bf16 rescoring band holds every document: beyond the
     # candidate buffer, so the row must be flagged as overflowed
