@@ -31,10 +31,12 @@
 // seed tiles (every 8th doc tile) are scored first; k_seed_bound / k_seed_hist /
 // k_seed_refine derive from them a lower bound of each query's k-th composite
 // (a 22-bit bucket edge); the other tiles append every composite at or above it
-// while they are scored (fp32 and uint8 then write no score rows for them), and
-// step 4 scans only the seed tiles. k_select_first falls back to the full row
-// (no bound, too many appended, or a refinement needed); such a query is listed
-// and its rows are scored again before steps 3 and 4.
+// while they are scored (fp32 and uint8 then write no score rows for them and do
+// not count them in the histogram), and step 4 scans only the seed tiles.
+// k_select_first falls back to the full row (no bound, too many appended, or a
+// refinement needed); such a query is listed, its other tiles are scored and
+// counted again, and a second k_select_first pass redoes its step 2 from the
+// complete histogram before steps 3 and 4.
 #include "gs_internal.h"
 
 namespace gs {
