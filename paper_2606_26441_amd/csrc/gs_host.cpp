@@ -676,8 +676,7 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     float* blk_max = nullptr;
     int32_t* blk_first = nullptr;
     if ((rc = dev_upload(ix->allocs, ix->bytes, L.blk_max.data(), L.blk_max.size(), &blk_max, s))) return done(rc);
-    if ((rc = dev_upload(ix->allocs, ix->bytes, L.blk_first.data(), L.blk_first.size(), &blk_first, s,
-                         kMaxChunk / kBlock)))
+    if ((rc = dev_upload(ix->allocs, ix->bytes, L.blk_first.data(), L.blk_first.size(), &blk_first, s)))
         return done(rc);
     d.blk_first = blk_first;
     {
