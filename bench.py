@@ -527,6 +527,11 @@ def main():
                                "kind": "oracle",
                                "sample": "first %d of the %d queries, full %d-doc collection, exact fp64 top-%d "
                                          "with full sort; %.1f s wall" % (s, nq, n_docs, args.k, cpu_s)}
+        t0 = time.time()
+        oracle.topk_f64(docs, queries.subset(np.arange(1)), args.k, n_threads=1)
+        out["cpu_single_thread"] = {"ms_per_query": round((time.time() - t0) * 1e3, 1),
+                                    "sample": "the oracle on the first query, one thread"}
+        log("CPU oracle, one thread: %.0f ms per query" % out["cpu_single_thread"]["ms_per_query"])
         # full-size parity of the timed launch configuration on the same sample
         checked = {}
         rid8 = rsc8 = None
