@@ -690,7 +690,11 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
         }
         uint8_t *pd = nullptr, *pb = nullptr;
         if ((rc = dev_upload(ix->allocs, ix->bytes, dense.data(), dense.size(), &pd, s))) return done(rc);
-        if ((rc = dev_upload(ix->allocs, ix->bytes, b8.data(), b8.size(), &pb, s, kPostSlack))) return done(rc);
+        // only the fp32 and bf16 kernels read the byte form; a uint8 index keeps a placeholder
+        const bool keep_b8 = precision != kU8;
+        if ((rc = dev_upload(ix->allocs, ix->bytes, keep_b8 ? b8.data() : nullptr, keep_b8 ? b8.size() : 0, &pb, s,
+                             keep_b8 ? kPostSlack : 0)))
+            return done(rc);
         d.term_dense = pd;
         d.post_b8 = pb;
         ix->n_dense = 0;
