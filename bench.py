@@ -54,6 +54,7 @@ def parse():
                     help="other precision[:kernel] forms to time (comma list, or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16, help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--profile", action="store_true", help="main form only, no CPU leg (for profiler runs)")
+    ap.add_argument("--lds-probe", action="store_true", help="only the LDS atomic-add yardstick (for profiler runs)")
     ap.add_argument("--no-fused", action="store_true", help="main form: scan every score row (no fused candidate filtering)")
     ap.add_argument("--batched", default="u8,bf16",
                     help="precisions for the 4,096-query uneven batch (autotuned, graph vs plain), or 'none'")
@@ -163,6 +164,30 @@ def score_error(oracle, docs, queries, s, k, rid, results):
         else:
             e["what"] = "returned fp32 score vs exact fp64 score"
         out[prec] = e
+    return out
+
+
+CU_COUNT, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
+
+
+def lds_atomic_rates(gs, torch, workgroups=2048, iters=1024, reps=5):
+    """LDS atomic-add throughput per accumulator type (lane-ops per clock per CU at 2.4 GHz)."""
+    sink = torch.empty(workgroups * 8, dtype=torch.uint8, device="cuda")
+    out = {}
+    for op in ("u32", "u64", "f32", "f64"):
+        for pattern, pname in ((0, "scattered"), (1, "consecutive")):
+            gs.lds_atomic_probe(op, pattern, workgroups, iters, sink)  # warm-up
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            n = 0
+            for _ in range(reps):
+                n += gs.lds_atomic_probe(op, pattern, workgroups, iters, sink)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            out["%s_%s" % (op, pname)] = round(n / (ms / 1e3) / CU_COUNT / CLOCK_HZ, 3)
+    out["unit"] = "lane-ops per clock per CU (%d CUs at %.1f GHz), %d x 512 lanes x %d adds into 64 KiB of LDS" % (
+        CU_COUNT, CLOCK_HZ / 1e9, workgroups, iters)
     return out
 
 
@@ -389,6 +414,9 @@ def main():
     import paper_2606_26441_amd as gs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.lds_probe:
+        print(json.dumps({"lds_atomic": lds_atomic_rates(gs, torch)}), flush=True)
+        return
     w = workload.WORKLOADS[args.workload]
     n_docs = args.n_docs or w.n_docs
     nq = args.batch or w.n_queries
@@ -414,6 +442,8 @@ def main():
     del src, dst
     torch.cuda.empty_cache()
     log("device copy yardstick: %.0f GB/s (read + write)" % copy_gbs)
+    lds_rates = lds_atomic_rates(gs, torch)
+    log("LDS atomic yardstick: %s" % lds_rates)
 
     log("main form: %s / %s, %d warmup + %d timed steps" % (args.precision, args.kernel, args.warmup, args.steps))
     main_res = time_form(gs, torch, docs, queries, args.k, args.precision, opts, args.steps, args.warmup,
@@ -479,6 +509,7 @@ def main():
                  "hbm_frac_whole_step": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "memory": {"index_bytes": main_res["device_bytes"], "workspace_bytes": main_res["ws_bytes"]},
         "hbm_copy_GBs": round(copy_gbs, 1),
+        "lds_atomic": lds_rates,
         "host_io": None if "host_ms" not in main_res else {
             "qps": round(nq / (float(np.median(main_res["host_ms"])) / 1e3), 2),
             "ms_per_batch": round(float(np.median(main_res["host_ms"])), 3),

@@ -53,11 +53,16 @@ enum gs_status {
 /* Posting-weight storage (the paper stores fp32, Sec. 3.1; compressed
  * posting scores are its future work (2), Sec. 8). */
 enum gs_precision {
-    GS_FP32 = 0, /* fp32 weights; products summed in 64-bit fixed point (per-query
-                    scale), scores are float */
+    GS_FP32 = 0, /* fp32 weights; scores are float, each within 1e-5 relative of the
+                    exact score. The doc-tiled kernels sum products in 64-bit fixed
+                    point (one scale per query: absolute error about 2^-51 of the
+                    query's largest product, times its term count); a query whose
+                    k-th score is too small for that error to stay within 2^-18 of
+                    it is summed again with fp64 accumulation of exact fp64 products */
     GS_BF16 = 1, /* bf16 weights (round to nearest even); approximate scores from
                     32-bit fixed-point sums (per-query scale bounding every doc's
-                    sum below 2^32 units), then fp64 rescoring of every candidate within the bf16 error band of
+                    sum below 2^32 units; the same wide-range check with 2^-12), then
+                    fp64 rescoring of every candidate within the bf16 error band of
                     the k-th score from the fp32 forward rows; scores are double and
                     equal the fp64 sum over shared terms in ascending term order */
     GS_U8 = 2    /* uint8 impacts q8(w) = round(w*255/3) (ties to even, saturated
@@ -79,9 +84,11 @@ enum gs_kernel {
                              atomics into the score array (the paper's Sec. 5.2 form) */
     GS_KERNEL_DOCPAR = 3, /* document-parallel: per (query, doc) gather over the
                              forward rows, no atomics (Sec. 5.3); needs GS_KEEP_FORWARD */
-    GS_KERNEL_SHARED = 4  /* batched: per (query group, doc tile), each posting segment
-                             is read once and applied to every query of the group
-                             that holds its term */
+    GS_KERNEL_SHARED = 4  /* batched shared traversal: the TILED work items on a
+                             persistent grid, taken tile by tile (every query of a
+                             doc tile on one XCD, longest queries first), so a
+                             tile's posting segments are read from HBM once and
+                             from that XCD's L2 for the other queries holding them */
 };
 
 #define GS_MAX_K 4096        /* largest k per query */
@@ -190,6 +197,27 @@ int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
                        int32_t* post_doc, float* post_w, float* blk_max, int32_t* blk_first_doc,
                        uint8_t* term_dense, uint8_t* post_b8);
 
+/*
+ * Host-only form of the per-query fixed-point plan that gs_batch_create computes
+ * (same code), for inspection and tests. The scatter-add of Sec. 4.1 (second
+ * eq.) is done in integers: each product w_q(t) * w_d(t) is rounded to units of
+ * 2^-F and the units are summed exactly.
+ * precision: GS_FP32 (64-bit sums: every product of the query below 2^51 units)
+ *   or GS_BF16 (32-bit sums: every document's sum below 2^32 units).
+ * q_weights [nnz], term_max [nnz], term_min [nnz] (host): per query term, its
+ *   weight, the largest stored weight of its posting list and the smallest
+ *   positive one (+inf if the list has none).
+ * out_F: the scale exponent. out_abs_err: bound on |fixed-point score - exact
+ *   score| for every document. out_wide_lim: the search sums the query again in
+ *   fp64 when its k-th approximate score may lie below this value (out_abs_err
+ *   over 2^-18 for fp32, 2^-12 for bf16); 0 when every positive score (at least
+ *   the smallest positive product) clears it. Any output may be NULL.
+ * Errors: GS_EINVAL (precision, nnz outside [0, GS_MAX_QUERY_NNZ], negative or
+ *   non-finite weights, term_min not positive).
+ */
+int32_t gs_query_plan_host(int32_t precision, const float* q_weights, const float* term_max, const float* term_min,
+                           int32_t nnz, int32_t* out_F, double* out_abs_err, double* out_wide_lim);
+
 /* --------------------------------------------------------- query batches -- */
 
 /*
@@ -256,7 +284,10 @@ int32_t gs_search_batch(gs_index index, gs_batch batch, void* workspace, size_t 
 
 /*
  * Convenience form: gs_batch_create + gs_search_batch + gs_batch_free.
- * Synchronous (the stream is synchronised before returning).
+ * Synchronous (the stream is synchronised before returning). Returns
+ * GS_ECAPACITY when the fp64-rescored error band of some query (GS_BF16) held
+ * more than 32768 documents: that query's row is then padding (see
+ * gs_batch_diagnostics); the other rows are valid.
  */
 int32_t gs_search(gs_index index, const int64_t* q_row_ptr, int32_t n_queries,
                   const int32_t* q_term_ids, const float* q_weights, int64_t q_nnz,
@@ -302,11 +333,21 @@ int32_t gs_autotune(gs_index index, gs_batch batch, void* workspace, size_t work
 /*
  * Per-query selection diagnostics of the last gs_search_batch on this batch
  * (host copy; call after the stream has been synchronised).
- * out [n_queries * 4] int32: candidates kept by the filter (with fused
- * filtering: those appended while scoring plus the seed tiles'), refinement passes
- * over the score array, bf16 band size (0 for other precisions), and an
- * overflow flag (1 if the candidate buffer overflowed; the row is then
- * invalid and the search call must be repeated with a larger workspace).
+ * out [n_queries * 8] int32 (host, caller-owned), per query:
+ *   [0] candidates kept by the filter (with fused filtering: those appended
+ *       while scoring plus the seed tiles');
+ *   [1] refinement passes over the score array;
+ *   [2] bf16 band size (0 for other precisions);
+ *   [3] overflow flag: 1 if more than 32768 documents lay inside the bf16 error
+ *       band of the k-th score (only when a huge number of documents tie
+ *       within that band). The buffer size is fixed, so the row is padding
+ *       (ids -1) and no workspace size avoids it; gs_search and the server
+ *       report GS_ECAPACITY for it;
+ *   [4] rows scored again: 0 no, 1 fallback of fused candidate filtering,
+ *       2 wide range (fixed-point error too large for the k-th score: every
+ *       tile summed again in fp64);
+ *   [5] 1 if fused candidate filtering produced the candidates;
+ *   [6], [7] 0.
  */
 int32_t gs_batch_diagnostics(gs_batch batch, int32_t* out);
 
@@ -332,6 +373,22 @@ int32_t gs_timing_read(double* score_ms, int64_t* score_launches, double* select
  * in each direction). Asynchronous. Errors: GS_EINVAL, GS_EHIP.
  */
 int32_t gs_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+/*
+ * LDS atomic-add throughput yardstick. The doc-tiled kernels scatter-add one
+ * product per posting into an LDS copy of a doc tile (the on-chip accumulation
+ * the paper leaves to future work (1), Sec. 8); the accumulator type is chosen
+ * by these rates. `workgroups` workgroups of 512 lanes each issue `iters`
+ * no-return atomic adds (iters a positive multiple of 16) into a 64 KiB LDS
+ * array. op: 0 uint32, 1 uint64, 2 float, 3 double. pattern: 0 scattered
+ * addresses (a per-lane pseudo-random sequence, as postings of many terms land
+ * in a tile), 1 consecutive words across each wavefront. sink (device, at least
+ * workgroups x 8 bytes) receives one value per workgroup. *lane_ops (may be
+ * NULL) receives workgroups x 512 x iters. Asynchronous on hip_stream; time it
+ * with events on that stream. Errors: GS_EINVAL, GS_EHIP.
+ */
+int32_t gs_lds_atomic_probe(int32_t op, int32_t pattern, int32_t workgroups, int32_t iters, void* sink,
+                            void* hip_stream, int64_t* lane_ops);
 
 /* ------------------------------------------------------------- serving -- */
 

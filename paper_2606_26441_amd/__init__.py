@@ -85,6 +85,8 @@ def _load() -> ctypes.CDLL:
     lib.gs_free_index.restype = None
     lib.gs_layout_host.argtypes = [vp, i64, vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.gs_layout_host.restype = i32
+    lib.gs_query_plan_host.argtypes = [i32, vp, vp, vp, i32, P(i32), P(ctypes.c_double), P(ctypes.c_double)]
+    lib.gs_query_plan_host.restype = i32
     lib.gs_batch_create.argtypes = [vp, vp, i32, vp, vp, i64, vp, i32, vp, P(vp)]
     lib.gs_batch_create.restype = i32
     lib.gs_batch_free.argtypes = [vp]
@@ -121,6 +123,8 @@ def _load() -> ctypes.CDLL:
     lib.gs_batch_diagnostics.restype = i32
     lib.gs_device_copy.argtypes = [vp, vp, sz, vp]
     lib.gs_device_copy.restype = i32
+    lib.gs_lds_atomic_probe.argtypes = [i32, i32, i32, i32, vp, vp, P(i64)]
+    lib.gs_lds_atomic_probe.restype = i32
     lib.gs_timing_enable.argtypes = [i32]
     lib.gs_timing_enable.restype = i32
     lib.gs_timing_read.argtypes = [P(ctypes.c_double), P(i64), P(ctypes.c_double), P(i64)]
@@ -174,6 +178,16 @@ def layout_host(row_ptr, terms, weights, vocab: int, precision="fp32"):
                               out["blk_first_doc"].ctypes.data, out["term_dense"].ctypes.data,
                               out["post_b8"].ctypes.data), "gs_layout_host")
     return out
+
+
+def query_plan_host(precision, q_weights, term_max, term_min):
+    """Per-query fixed-point plan (gs_query_plan_host): (F, abs_err bound, wide-range limit)."""
+    w, a, b = _np(q_weights, np.float32), _np(term_max, np.float32), _np(term_min, np.float32)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    F, e, lim = ctypes.c_int32(0), ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib.gs_query_plan_host(prec, w.ctypes.data, a.ctypes.data, b.ctypes.data, w.shape[0], ctypes.byref(F),
+                                  ctypes.byref(e), ctypes.byref(lim)), "gs_query_plan_host")
+    return int(F.value), float(e.value), float(lim.value)
 
 
 class Index:
@@ -337,8 +351,9 @@ class Batch:
         return self._h
 
     def diagnostics(self) -> np.ndarray:
-        """[n_queries, 4]: candidates, refinement passes, bf16 band size, overflow flag."""
-        out = np.zeros((self.n_queries, 4), dtype=np.int32)
+        """[n_queries, 8]: candidates, refinement passes, bf16 band size, overflow flag, rows scored
+        again (0 no, 1 fused-filtering fallback, 2 wide range: fp64 pass), fused filtering used, 0, 0."""
+        out = np.zeros((self.n_queries, 8), dtype=np.int32)
         _check(lib.gs_batch_diagnostics(self._h, out.ctypes.data), "gs_batch_diagnostics")
         return out
 
@@ -438,6 +453,18 @@ def device_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
     """Plain 16-byte-vector copy (traffic-counter yardstick)."""
     n = min(dst.numel() * dst.element_size(), src.numel() * src.element_size())
     _check(lib.gs_device_copy(dst.data_ptr(), src.data_ptr(), n, _stream_ptr(stream)), "gs_device_copy")
+
+
+LDS_ATOMIC_OPS = {"u32": 0, "u64": 1, "f32": 2, "f64": 3}
+
+
+def lds_atomic_probe(op: str, pattern: int, workgroups: int, iters: int, sink: torch.Tensor, stream=None) -> int:
+    """Launch the LDS atomic-add yardstick (asynchronous); returns the lane-ops it issues."""
+    n = ctypes.c_int64(0)
+    assert sink.numel() * sink.element_size() >= 8 * workgroups
+    _check(lib.gs_lds_atomic_probe(LDS_ATOMIC_OPS[op], int(pattern), int(workgroups), int(iters), sink.data_ptr(),
+                                   _stream_ptr(stream), ctypes.byref(n)), "gs_lds_atomic_probe")
+    return int(n.value)
 
 
 def timing_enable(on: bool = True):

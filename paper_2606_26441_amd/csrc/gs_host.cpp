@@ -90,6 +90,60 @@ int32_t gs::set_error(int32_t code, const std::string& msg) { return fail(code, 
 
 namespace {
 
+// ------------------------------------------------- fixed-point plan ------
+//
+// Per-query scale of the fixed-point sums (fp32 and bf16 weights; Sec. 4.1's
+// scatter-add of w_q(t) * w_d(t) done in integers). Products are rounded to
+// units of 2^-F and summed exactly.
+//  * fp32 (64-bit sums): every product of the query below 2^51 units, from the
+//    largest stored weight of each query term, so a sum of at most 256 products
+//    stays below 2^59.
+//  * bf16 (32-bit sums): every doc's sum below 2^32 units. A sum is at most
+//    sumprod * 2^F (sumprod: the query weights times their terms' largest stored
+//    weights) plus half a unit of rounding per product; F is the largest with
+//    sumprod * 2^F + m + 2 < 2^32.
+// abs_err bounds |fixed-point score - exact score|: half a unit per product plus
+// the conversions, (m + 1) units. wide_lim: the selection sends the query to the
+// fp64 pass when its k-th approximate score may lie below abs_err / rho, rho the
+// relative budget of that error (fp32: 2^-18, so that two scores compared across
+// the k-th boundary stay within the 1e-5 rule; bf16: 2^-12, small beside the
+// error band's bf16 width). A positive score is at least the smallest positive
+// product (query weight times its term's smallest positive stored weight); when
+// that is at or above the limit, no score can miss the budget and wide_lim is 0.
+struct FixedPlan {
+    int F = 0;
+    double scale = 1.0, abs_err = 0.0, wide_lim = 0.0;
+};
+
+FixedPlan fixed_point_plan(int precision, int64_t m, const float* w, const float* tmax, const float* tmin) {
+    FixedPlan p;
+    double maxprod = 0.0, sumprod = 0.0, minprod = std::numeric_limits<double>::infinity();
+    for (int64_t j = 0; j < m; j++) {
+        const double pm = (double)w[j] * (double)tmax[j];
+        maxprod = std::max(maxprod, pm);
+        sumprod += pm;
+        if (w[j] > 0.0f && std::isfinite(tmin[j])) minprod = std::min(minprod, (double)w[j] * (double)tmin[j]);
+    }
+    int ex = 0;
+    if (precision == kBF16) {
+        if (sumprod > 0.0) {
+            (void)std::frexp((4294967296.0 - (double)m - 3.0) / (sumprod * (1.0 + 1e-9)), &ex);
+            p.F = ex - 1;  // 2^F <= (2^32 - m - 3) / sumprod
+        }
+    } else {
+        if (maxprod > 0.0) (void)std::frexp(maxprod * (1.0 + 1e-9), &ex);  // maxprod < 2^ex
+        p.F = 51 - ex;
+    }
+    p.F = std::min(1000, std::max(-1000, p.F));
+    p.scale = std::ldexp(1.0, -p.F);
+    p.abs_err = (double)(m + 1) * p.scale * (1.0 + 1e-6);
+    if (precision != kU8) {
+        const double lim = p.abs_err / std::ldexp(1.0, precision == kFP32 ? -18 : -12);
+        p.wide_lim = lim <= minprod ? 0.0 : lim;
+    }
+    return p;
+}
+
 // ----------------------------------------------------------- CSR checks --
 
 struct Rows {
@@ -337,8 +391,8 @@ struct gs_index_s {
 // pinned host stage of the same layout): the per-query arrays first (copied
 // whole on every update), then the per-term arrays (copied up to the terms in use).
 struct BatchLayout {
-    size_t rp = 0, k = 0, fs = 0, delta = 0, scale = 0, err = 0, work = 0, diag = 0, head = 0;
-    size_t term = 0, w = 0, w8 = 0, fx = 0, bump = 0, total = 0;
+    size_t rp = 0, k = 0, fs = 0, delta = 0, scale = 0, err = 0, wide = 0, work = 0, diag = 0, head = 0;
+    size_t term = 0, w = 0, w8 = 0, fx = 0, total = 0;
     BatchLayout(size_t nq, size_t nz) {
         size_t at = 0;
         auto take = [&](size_t bytes) {
@@ -352,14 +406,14 @@ struct BatchLayout {
         delta = take(nq * 4);
         scale = take(nq * 8);
         err = take(nq * 8);
+        wide = take(nq * 8);
         work = take(nq * 8);
-        diag = take(nq * 16);
+        diag = take(nq * kDiagWords * 4);
         head = at;
         term = take(nz * 4);
         w = take(nz * 4);
         w8 = take(nz * 4);
         fx = take(nz * 8);
-        bump = take(nz * 4);
         total = at;
     }
 };
@@ -370,14 +424,13 @@ struct gs_batch_s {
     int32_t n_queries = 0, k_max = 0;  // capacity in queries (launch shapes use it)
     int64_t q_nnz = 0;                 // capacity in query terms
     int32_t n_active = 0;              // queries set by the last update
-    bool any_raise = true;             // some product of the batch may round to 0 units (fixed point)
     BatchLayout lay{0, 0};
     uint8_t* dmem = nullptr;    // device: every array of the batch
     uint8_t* stage = nullptr;   // pinned host copy of the same layout (update staging)
     hipEvent_t copied = nullptr;  // recorded after the last update's copies
     bool copy_pending = false;
     DevBatch dev{};
-    int32_t* diag = nullptr;  // [n_queries * 4] (inside dmem)
+    int32_t* diag = nullptr;  // [n_queries * kDiagWords] (inside dmem)
     ~gs_batch_s() {
         if (copy_pending) (void)hipEventSynchronize(copied);
         if (copied) (void)hipEventDestroy(copied);
@@ -573,6 +626,23 @@ int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
         if (term_dense) std::memcpy(term_dense, dense.data(), dense.size());
         if (post_b8) std::memcpy(post_b8, b8.data(), b8.size());
     }
+    return GS_OK;
+}
+
+int32_t gs_query_plan_host(int32_t precision, const float* q_weights, const float* term_max, const float* term_min,
+                           int32_t nnz, int32_t* out_F, double* out_abs_err, double* out_wide_lim) {
+    g_err.clear();
+    if (precision != kFP32 && precision != kBF16) return fail(GS_EINVAL, "precision must be GS_FP32 or GS_BF16");
+    if (nnz < 0 || nnz > kMaxQueryNnz) return fail(GS_EINVAL, "nnz outside [0, GS_MAX_QUERY_NNZ]");
+    if (nnz > 0 && (!q_weights || !term_max || !term_min)) return fail(GS_EINVAL, "null array");
+    for (int32_t j = 0; j < nnz; j++)
+        if (!(q_weights[j] >= 0.0f) || !std::isfinite(q_weights[j]) || !(term_max[j] >= 0.0f) ||
+            !std::isfinite(term_max[j]) || !(term_min[j] > 0.0f))
+            return fail(GS_EINVAL, "weights must be finite and >= 0, term_min > 0 (+inf for an all-zero list)");
+    const FixedPlan p = fixed_point_plan(precision, nnz, q_weights, term_max, term_min);
+    if (out_F) *out_F = p.F;
+    if (out_abs_err) *out_abs_err = p.abs_err;
+    if (out_wide_lim) *out_wide_lim = p.wide_lim;
     return GS_OK;
 }
 
@@ -790,12 +860,12 @@ int32_t gs_batch_reserve(gs_index ix, int32_t max_queries, int64_t max_nnz, int3
     d.q_w = (const float*)(m + L.w);
     d.q_w8 = (const int32_t*)(m + L.w8);
     d.q_fx = (const double*)(m + L.fx);
-    d.q_bump = (const int32_t*)(m + L.bump);
     d.k = (const int32_t*)(m + L.k);
     d.first_shift = (const int32_t*)(m + L.fs);
     d.delta = (const float*)(m + L.delta);
     d.q_scale = (const double*)(m + L.scale);
     d.q_abs_err = (const double*)(m + L.err);
+    d.q_wide_lim = (const double*)(m + L.wide);
     d.q_work = (const int64_t*)(m + L.work);
     b->diag = (int32_t*)(m + L.diag);
     // an empty batch until the first update: every slot is a query with no terms and k = 0
@@ -839,30 +909,31 @@ int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, co
     float* delta = (float*)(h + L.delta);
     double* qscale = (double*)(h + L.scale);
     double* qerr = (double*)(h + L.err);
+    double* qwide = (double*)(h + L.wide);
     int64_t* qwork = (int64_t*)(h + L.work);
     int32_t* w8 = (int32_t*)(h + L.w8);
     double* qfx = (double*)(h + L.fx);
-    int32_t* qbump = (int32_t*)(h + L.bump);
     // slots past n_queries become empty queries with k = 0 (no work, padding-only rows)
     for (int32_t q = 0; q <= cap; q++) rp[q] = q <= n_queries ? (q_row_ptr ? q_row_ptr[q] : 0) : q_nnz;
     for (int32_t q = 0; q < cap; q++) kk[q] = q < n_queries ? k[q] : 0;
-    std::memset(h + L.diag, 0, (size_t)cap * 16);
+    std::memset(h + L.diag, 0, (size_t)cap * kDiagWords * 4);
     if (q_nnz > 0) {
         std::memcpy(h + L.term, r.term, (size_t)q_nnz * 4);
         std::memcpy(h + L.w, r.w, (size_t)q_nnz * 4);
     }
+    std::vector<float> tmax, tmin;
     for (int32_t q = 0; q < cap; q++) {
         uint64_t maxs = 0;
-        double maxprod = 0.0, sumprod = 0.0;
         const int64_t m = rp[q + 1] - rp[q];
         qwork[q] = 0;
+        tmax.resize((size_t)m);
+        tmin.resize((size_t)m);
         for (int64_t j = rp[q]; j < rp[q + 1]; j++) {
             qwork[q] += ix->term_len[(size_t)r.term[j]];
             w8[j] = q8(r.w[j]);
             maxs += (uint64_t)w8[j] * 255u;
-            const double pm = (double)r.w[j] * (double)ix->term_max[(size_t)r.term[j]];
-            maxprod = std::max(maxprod, pm);
-            sumprod += pm;  // bound on any doc's score: the largest stored weight of every query term
+            tmax[(size_t)(j - rp[q])] = ix->term_max[(size_t)r.term[j]];
+            tmin[(size_t)(j - rp[q])] = ix->term_min[(size_t)r.term[j]];
         }
         if (ix->precision == kU8) {
             int hb = 0;
@@ -871,34 +942,14 @@ int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, co
         } else {
             fshift[q] = kFirstShiftFloat;
         }
-        // fixed point in units of 2^-F. fp32 (64-bit sums): every product of this query below
-        // 2^51 units, so a sum of at most 256 products stays below 2^59. bf16 (32-bit sums):
-        // every doc's sum below 2^32 units; it is at most sumprod * 2^F plus one unit of
-        // rounding per product, and F is the largest with sumprod * 2^F + m + 2 < 2^32.
-        int ex = 0, F = 0;
-        if (ix->precision == kBF16) {
-            if (sumprod > 0.0) {
-                (void)std::frexp((4294967296.0 - (double)m - 3.0) / (sumprod * (1.0 + 1e-9)), &ex);
-                F = ex - 1;  // 2^F <= (2^32 - m - 3) / sumprod
-            }
-        } else {
-            if (maxprod > 0.0) (void)std::frexp(maxprod * (1.0 + 1e-9), &ex);  // maxprod < 2^ex
-            F = 51 - ex;
-        }
-        F = std::min(1000, std::max(-1000, F));
-        qscale[q] = std::ldexp(1.0, -F);
-        // each product is within half a unit (or, raised from 0 to 1, within one unit) of exact
-        qerr[q] = (double)(m + 1) * std::ldexp(1.0, -F) * (1.0 + 1e-6);
-        for (int64_t j = rp[q]; j < rp[q + 1]; j++) {
-            qfx[j] = std::ldexp((double)r.w[j], F);
-            // a positive product of this term can round to 0 units only if its smallest one is below 1 unit
-            qbump[j] = !(qfx[j] * (double)ix->term_min[(size_t)r.term[j]] >= 1.0);
-        }
+        const FixedPlan fp = fixed_point_plan(ix->precision, m, r.w + rp[q], tmax.data(), tmin.data());
+        qscale[q] = fp.scale;
+        qerr[q] = fp.abs_err;
+        qwide[q] = fp.wide_lim;
+        for (int64_t j = rp[q]; j < rp[q + 1]; j++) qfx[j] = std::ldexp((double)r.w[j], fp.F);
         // bf16 form: relative error of a stored weight (2^-8) and of the fp32 score (2^-24, with margin)
         delta[q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -23)) - 1.0) * (1.0 + 1e-6));
     }
-    b->any_raise = false;
-    for (int64_t j = 0; j < rp[n_queries]; j++) b->any_raise |= qbump[j] != 0;
     // copies on the caller's stream, ordered after the searches already enqueued on it
     hipStream_t s = (hipStream_t)hip_stream;
     auto up = [&](size_t off, size_t bytes) -> hipError_t {
@@ -909,7 +960,6 @@ int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, co
     if (e == hipSuccess) e = up(L.w, (size_t)q_nnz * 4);
     if (e == hipSuccess) e = up(L.w8, (size_t)q_nnz * 4);
     if (e == hipSuccess) e = up(L.fx, (size_t)q_nnz * 8);
-    if (e == hipSuccess) e = up(L.bump, (size_t)q_nnz * 4);
     if (e == hipSuccess) e = hipEventRecord(b->copied, s);
     if (e == hipSuccess) {
         b->copy_pending = true;
@@ -1030,9 +1080,8 @@ int32_t plan_search(gs_index ix, gs_batch b, size_t workspace_bytes_, const gs_s
 // (id -1, score 0). A direct search passes the queries of the last update, a
 // graph the whole capacity (it is replayed after updates of any size).
 int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int32_t qt, const ScoreOpts& so_in,
-                       int32_t* out_ids, void* out_scores, hipStream_t s, bool timing, int raise = -1) {
+                       int32_t* out_ids, void* out_scores, hipStream_t s, bool timing) {
     ScoreOpts so = so_in;
-    so.raise = raise >= 0 ? raise : (b->any_raise ? 1 : 0);
     // Fused candidate filtering (doc-tiled kernels): every stride-th tile seeds a lower bound
     // of the k-th composite; the other tiles append their candidates while they are scored.
     // The seed tiles should hold several times k documents: stride 8 up to k = 1024, 4 up to
@@ -1080,11 +1129,15 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int
         }
         if (e == hipSuccess) {
             SpanRecorder rec(timing ? 1 : -1, s);
-            std::function<hipError_t()> rescore;
-            if (so.seed_stride > 0 && ix->precision != kBF16)
-                rescore = [&] { return launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 3); };
-            e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s, so.tile_shift,
-                              so.seed_stride, rescore);
+            // Between the two first-digit selection passes: the rows of the listed queries.
+            // Fused fp32 / uint8 queries that fell back get their non-seed tiles scored (phase 3);
+            // fixed-point queries found wide range get every tile scored in fp64 (phase 4).
+            const bool doc_tiled = so.kernel == GS_KERNEL_TILED || so.kernel == GS_KERNEL_SHARED;
+            const bool fixed = doc_tiled && ix->precision != kU8;
+            const bool phase3 = so.seed_stride > 0 && ix->precision != kBF16;
+            const int acc = ix->precision == kU8 ? kAccInteger : (doc_tiled ? kAccFixed : kAccFloat);
+            e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s, acc, so.tile_shift,
+                              so.seed_stride, phase3 ? &so : nullptr, fixed);
             rec.end(s);
         }
         if (e != hipSuccess)
@@ -1104,20 +1157,28 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int
 
 }  // namespace
 
+namespace {
+
+// After a synchronised search: GS_ECAPACITY when the rescored band of some query did not
+// fit its buffer (bf16; that row holds padding), else GS_OK.
+int32_t check_overflow(gs_batch b) {
+    if (b->n_active == 0) return GS_OK;
+    std::vector<int32_t> d((size_t)b->n_active * kDiagWords);
+    const hipError_t e = hipMemcpy(d.data(), b->diag, d.size() * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(GS_EHIP, std::string("diagnostics: ") + hipGetErrorString(e));
+    for (int32_t q = 0; q < b->n_active; q++)
+        if (d[(size_t)q * kDiagWords + 3])
+            return fail(GS_ECAPACITY, "query " + std::to_string(q) + ": more than " + std::to_string(kCandCap) +
+                                          " documents inside the bf16 error band of its k-th score");
+    return GS_OK;
+}
+
+}  // namespace
+
 struct gs_graph_s {
     int device = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // the search as captured, for replays after an update that the captured kernels
-    // do not cover (a product that may round to 0 units): then it is enqueued directly
-    int raise = 1;
-    gs_index index = nullptr;
-    gs_batch batch = nullptr;
-    void* workspace = nullptr;
-    int32_t qt = 1;
-    ScoreOpts so{};
-    int32_t* out_ids = nullptr;
-    void* out_scores = nullptr;
     ~gs_graph_s() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -1169,15 +1230,7 @@ int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspa
         delete gr;
         return fail(GS_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
-    gr->raise = b->any_raise ? 1 : 0;
-    gr->index = ix;
-    gr->batch = b;
-    gr->workspace = workspace;
-    gr->qt = qt;
-    gr->so = so;
-    gr->out_ids = out_ids;
-    gr->out_scores = out_scores;
-    rc = enqueue_search(ix, b, b->n_queries, workspace, qt, so, out_ids, out_scores, cs, false, gr->raise);
+    rc = enqueue_search(ix, b, b->n_queries, workspace, qt, so, out_ids, out_scores, cs, false);
     e = hipStreamEndCapture(cs, &gr->graph);
     (void)hipStreamDestroy(cs);
     if (rc != GS_OK) {
@@ -1262,9 +1315,6 @@ int32_t gs_graph_launch(gs_graph gr, void* hip_stream) {
     g_err.clear();
     if (!gr) return fail(GS_EINVAL, "graph is null");
     DeviceGuard g(gr->device);
-    if (gr->batch->any_raise && !gr->raise)
-        return enqueue_search(gr->index, gr->batch, gr->batch->n_queries, gr->workspace, gr->qt, gr->so, gr->out_ids,
-                              gr->out_scores, (hipStream_t)hip_stream, false, 1);
     GS_HIP(hipGraphLaunch(gr->exec, (hipStream_t)hip_stream));
     return GS_OK;
 }
@@ -1284,8 +1334,9 @@ int32_t gs_search(gs_index ix, const int64_t* q_row_ptr, int32_t n_queries, cons
     if (rc != GS_OK) return rc;
     rc = gs_search_batch(ix, b, workspace, workspace_bytes_, out_ids, out_scores, opts, hip_stream);
     hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
-    gs_batch_free(b);
     if (rc == GS_OK && e != hipSuccess) rc = fail(GS_EHIP, std::string("search: ") + hipGetErrorString(e));
+    if (rc == GS_OK) rc = check_overflow(b);
+    gs_batch_free(b);
     return rc;
 }
 
@@ -1335,12 +1386,25 @@ int32_t gs_device_copy(void* dst, const void* src, size_t bytes, void* hip_strea
     return GS_OK;
 }
 
+int32_t gs_lds_atomic_probe(int32_t op, int32_t pattern, int32_t workgroups, int32_t iters, void* sink,
+                            void* hip_stream, int64_t* lane_ops) {
+    g_err.clear();
+    if (op < 0 || op > 3) return fail(GS_EINVAL, "op must be 0 (uint32), 1 (uint64), 2 (float) or 3 (double)");
+    if (pattern != 0 && pattern != 1) return fail(GS_EINVAL, "pattern must be 0 or 1");
+    if (workgroups < 1 || iters < 16 || iters % 16) return fail(GS_EINVAL, "workgroups >= 1, iters a positive multiple of 16");
+    if (!sink) return fail(GS_EINVAL, "null sink");
+    (void)hipGetLastError();
+    GS_HIP(launch_lds_atomic(op, pattern, workgroups, iters, sink, (hipStream_t)hip_stream));
+    if (lane_ops) *lane_ops = (int64_t)workgroups * 512 * iters;
+    return GS_OK;
+}
+
 int32_t gs_batch_diagnostics(gs_batch b, int32_t* out) {
     g_err.clear();
     if (!b || !out) return fail(GS_EINVAL, "null argument");
     if (b->n_queries == 0) return GS_OK;
     DeviceGuard g(b->device);
-    GS_HIP(hipMemcpy(out, b->diag, (size_t)b->n_queries * 16, hipMemcpyDeviceToHost));
+    GS_HIP(hipMemcpy(out, b->diag, (size_t)b->n_queries * kDiagWords * 4, hipMemcpyDeviceToHost));
     return GS_OK;
 }
 

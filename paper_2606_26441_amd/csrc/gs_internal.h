@@ -1,11 +1,10 @@
 // Internal declarations shared by the host side (gs_host.cpp) and the HIP
-// kernels (gs_score.hip, gs_topk.hip) of libgpusparse.so.
+// kernels (gs_score.hip, gs_topk.hip, gs_yardstick.hip) of libgpusparse.so.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <functional>
 #include <string>
 
 struct gs_batch_s;
@@ -27,6 +26,7 @@ constexpr int kCandCap = 32768;       // candidates kept per query by the filter
 constexpr int kFusedCap = 24576;      // of which appended while scoring (fused filtering)
 constexpr int kRefinePasses = 6;      // enough to resolve any 64-bit composite key
 constexpr int kFirstShiftFloat = 52;  // first digit of a float key: bits 30..20
+constexpr int kDiagWords = 8;         // per-query words of gs_batch_diagnostics
 
 enum Precision { kFP32 = 0, kBF16 = 1, kU8 = 2 };
 
@@ -83,12 +83,15 @@ struct DevBatch {
     const int32_t* first_shift;  // [n] position of the first selection digit in the composite key
     const float* delta;        // [n] bf16 relative error bound per query (GS_BF16), else null
     // fixed-point accumulation (GS_FP32, GS_BF16): each product w_q * w_d is rounded to an
-    // integer number of units 2^-F(q) and summed exactly as an unsigned 64-bit integer; F(q) is
-    // chosen per query so that every product of the query stays below 2^51 units.
+    // integer number of units 2^-F(q) and summed exactly as an unsigned integer (64-bit for
+    // fp32, every product below 2^51 units; 32-bit for bf16, every doc's sum below 2^32 units).
     const double* q_fx;        // [q_nnz] w_q * 2^F(q) (exact)
-    const int32_t* q_bump;     // [q_nnz] 1 if a positive product of the term can round to 0 units
     const double* q_scale;     // [n] 2^-F(q)
     const double* q_abs_err;   // [n] bound on |fixed-point sum - exact sum|
+    // [n] wide-range check of the fixed-point sums: a query whose k-th approximate score may
+    // lie below this value (its error bound over the relative budget of its precision) is
+    // scored again with fp64 accumulation; 0 when the bound holds for every positive score.
+    const double* q_wide_lim;
     const int64_t* q_work;     // [n] postings of the query's terms (work estimate)
 };
 
@@ -110,7 +113,9 @@ struct SelState {
     unsigned long long bound;
     int32_t fused;              // 1 while the appended candidates stand in for the row scan
     int32_t fused_over;         // the appends passed kFusedCap
-    int32_t rescore;            // fell back after its non-seed rows were left unwritten: score them again
+    // 1: fell back from fused filtering after its non-seed rows were left unwritten (score
+    // them again, fixed point); 2: wide range (score every tile again, fp64 accumulation)
+    int32_t rescore;
     int32_t pad_;
 };
 
@@ -128,7 +133,7 @@ struct Workspace {
     int32_t* order;               // [qt] persistent kernel: query order within the tile
     uint32_t* counters;           // [16]: [0..7] persistent kernel per-XCD work counters,
                                   // [8] queries in rescore_list
-    int32_t* rescore_list;        // [qt] fused filtering: queries whose rows are scored again
+    int32_t* rescore_list;        // [qt] queries whose rows are scored again (SelState::rescore)
     int64_t ld;                   // row stride of the score arrays (n_docs rounded up to 64)
 };
 
@@ -139,21 +144,21 @@ struct ScoreOpts {
     int kernel;
     int tile_shift;   // doc tile of the TILED/SHARED kernels = 1 << tile_shift docs
     int chunk;        // postings per work item
-    int raise = 1;    // fixed point: some positive product of the batch may round to 0 units
     int seed_stride = 0;  // fused candidate filtering: every seed_stride-th doc tile seeds the bound (0: off)
 };
 
 // Doc tiles of a scoring launch: phase 0 all tiles, phase 1 the seed tiles
 // (multiples of stride), phase 2 the others, phase 3 the others again for the
-// queries that fell back from fused filtering (their rows). v is the launch's
-// tile index.
+// queries that fell back from fused filtering (their rows), phase 4 all tiles
+// again for the wide-range queries (fp64 accumulation). v is the launch's tile
+// index.
 __host__ __device__ inline int64_t phase_tiles(int phase, int stride, int64_t n_tiles) {
-    if (phase == 0) return n_tiles;
+    if (phase == 0 || phase == 4) return n_tiles;
     const int64_t seeds = (n_tiles + stride - 1) / stride;
     return phase == 1 ? seeds : n_tiles - seeds;
 }
 __host__ __device__ inline int64_t phase_tile(int phase, int stride, int64_t v) {
-    if (phase == 0) return v;
+    if (phase == 0 || phase == 4) return v;
     if (phase == 1) return v * stride;
     return (v / (stride - 1)) * stride + v % (stride - 1) + 1;
 }
@@ -169,20 +174,33 @@ int32_t batch_update(struct ::gs_batch_s* b, const int64_t* q_row_ptr, int32_t n
 hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s);
 hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                               const ScoreOpts& o, const Workspace& ws, hipStream_t s, int phase = 0);
+// fp64-accumulating pass over every doc tile for the queries listed as wide range
+// (fp32, bf16); a no-op when none is listed
+hipError_t launch_score_wide(const DevIndex& ix, const DevBatch& qb, int32_t q0, const Workspace& ws, hipStream_t s);
 hipError_t launch_score_atomic(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                                const ScoreOpts& o, const Workspace& ws, hipStream_t s);
 hipError_t launch_score_docpar(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                                const ScoreOpts& o, const Workspace& ws, hipStream_t s);
 hipError_t launch_hist1(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                         const Workspace& ws, hipStream_t s);
+// ---- launchers (gs_yardstick.hip) ----
 hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s);
+// LDS atomic-add throughput: op 0 uint32, 1 uint64, 2 float, 3 double; pattern 0 scattered, 1 consecutive
+hipError_t launch_lds_atomic(int op, int pattern, int workgroups, int iters, void* sink, hipStream_t s);
 hipError_t launch_fill(void* p, int64_t n_words, uint32_t v, hipStream_t s);  // p[0..n) = v (a kernel, capturable)
 
 // ---- launchers (gs_topk.hip) ----
+// Accumulation behind the scores: fixed point (doc-tiled kernels, fp32 and bf16 weights:
+// absolute error bound, wide-range check), float (global-atomic and document-parallel
+// kernels: relative error bound) or integer (uint8 impacts: exact).
+enum AccKind { kAccFixed = 0, kAccFloat = 1, kAccInteger = 2 };
+// Between the two k_select_first passes, the rows of the listed queries are scored again:
+// with phase3 (non-null) the fused fp32 / uint8 queries that fell back (phase 3 of
+// launch_score_tiled with these options), with wide the wide-range queries (fp64 pass).
 hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                          const Workspace& ws, int32_t* out_ids, void* out_scores, int32_t* diag,
-                         hipStream_t s, int tile_shift = 0, int seed_stride = 0,
-                         const std::function<hipError_t()>& after_first = nullptr);
+                         hipStream_t s, int acc, int tile_shift = 0, int seed_stride = 0,
+                         const ScoreOpts* phase3 = nullptr, bool wide = false);
 // fused filtering: the bound of every query of the tile from its seed-tile histogram
 hipError_t launch_seed_bound(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                              const Workspace& ws, hipStream_t s, int tile_shift, int stride);

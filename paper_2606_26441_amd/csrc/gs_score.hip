@@ -101,28 +101,13 @@ __device__ __forceinline__ T wave_sum(T v) {
 // weights are widened first). One fp64 FMA forms qd * w_d + 2^52 with a single
 // rounding; the per-query F keeps every product below 2^51, so the result lies in
 // [2^52, 2^53) where the fp64 spacing is 1 and its low bits are the product
-// rounded to the nearest integer. A positive product that rounds to 0 is raised
-// to 1, so a product is zero exactly when w_q * w_d is zero.
-// The same product without the raise, for batches in which every positive
-// product is at least one unit (decided per query term on the host).
-__device__ __forceinline__ unsigned long long fx_product_units(double qd, uint32_t wbits) {
-    constexpr double kTwo52 = 4503599627370496.0;
-    const double wd = (double)__uint_as_float(wbits);
-    return (unsigned long long)__double_as_longlong(__builtin_fma(qd, wd, kTwo52)) - 0x4330000000000000ull;
-}
-
+// rounded to the nearest integer (within half a unit of it). A product below half
+// a unit becomes 0; the selection's wide-range check covers the queries where
+// that could matter (their rows are summed again in fp64).
 __device__ __forceinline__ unsigned long long fx_product(double qd, uint32_t wbits) {
     constexpr double kTwo52 = 4503599627370496.0;
     const double wd = (double)__uint_as_float(wbits);
-    const unsigned long long r =
-        (unsigned long long)__double_as_longlong(__builtin_fma(qd, wd, kTwo52)) - 0x4330000000000000ull;
-    return r | (unsigned long long)((r == 0ull) & (wbits != 0u));  // qd > 0 for every processed term
-}
-
-template <bool RB>
-__device__ __forceinline__ unsigned long long fx_prod(double qd, uint32_t wbits) {
-    if constexpr (RB) return fx_product(qd, wbits);
-    else return fx_product_units(qd, wbits);
+    return (unsigned long long)__double_as_longlong(__builtin_fma(qd, wd, kTwo52)) - 0x4330000000000000ull;
 }
 
 __device__ __forceinline__ uint32_t stored_bits(const void* p, int64_t i, std::integral_constant<int, kFP32>) {
@@ -135,8 +120,9 @@ __device__ __forceinline__ uint32_t stored_bits(const void* p, int64_t i, std::i
 // Write a finished LDS tile to the score array (fp32 bits or int32) and add its
 // first-digit histogram (composite key (score bits, ~doc id), digit at fs).
 // Accumulator forms: kAccInt (int32 sums, written as they are), kAccFx32 and
-// kAccFx64 (unsigned fixed point in units of `scale`, written as fp32 bits).
-enum AccForm { kAccInt = 0, kAccFx32 = 1, kAccFx64 = 2 };
+// kAccFx64 (unsigned fixed point in units of `scale`, written as fp32 bits), kAccF64
+// (fp64 sums of exact fp64 products, the wide-range pass, written as fp32 bits).
+enum AccForm { kAccInt = 0, kAccFx32 = 1, kAccFx64 = 2, kAccF64 = 3 };
 
 // Fused candidate filtering: append the composites c >= bound of the lanes that
 // take one to the query's candidate buffer (one atomic per wavefront; hits are
@@ -204,6 +190,10 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
             const unsigned long long* acc = (const unsigned long long*)acc_v;
 #pragma unroll
             for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)acc[4 * i + j] * scale));
+        } else if constexpr (AF == kAccF64) {
+            const double* acc = (const double*)acc_v;
+#pragma unroll
+            for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)acc[4 * i + j]);
         } else {
             const uint4 u = reinterpret_cast<const uint4*>(acc_v)[i];
             v[0] = u.x; v[1] = u.y; v[2] = u.z; v[3] = u.w;
@@ -231,6 +221,7 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
     for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
         uint32_t v;
         if constexpr (AF == kAccFx64) v = __float_as_uint((float)((double)((const unsigned long long*)acc_v)[i] * scale));
+        else if constexpr (AF == kAccF64) v = __float_as_uint((float)((const double*)acc_v)[i]);
         else if constexpr (AF == kAccFx32) v = __float_as_uint((float)((double)((const uint32_t*)acc_v)[i] * scale));
         else v = ((const uint32_t*)acc_v)[i];
         if (write) Sq[i] = v;
@@ -255,12 +246,17 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
 // of CH postings; wavefronts take chunks round-robin, each lane loads CH/64
 // postings (coalesced across the wavefront) before issuing its LDS adds.
 
-// fp32 weights: 64-bit fixed point (exact enough for the 1e-5 score rule at any
-// score). bf16 weights: 32-bit fixed point, whose scores only choose the
-// candidates that are rescored in fp64. uint8 impacts: int32.
-template <int P>
+// fp32 weights: 64-bit fixed point. Its error is absolute, (m+1) half-units of
+// 2^-F with 2^-F about 2^-51 of the query's largest product: far inside the 1e-5
+// relative rule for scores near the query's scale, not for scores many orders of
+// magnitude below it. The selection checks each query's k-th score against that
+// bound and sends the queries where it could fail to the fp64 pass (W).
+// bf16 weights: 32-bit fixed point, whose scores only choose the candidates that
+// are rescored in fp64 (the same check keeps the error band narrow). uint8
+// impacts: int32, exact. W: fp64 accumulation of exact fp64 products.
+template <int P, bool W = false>
 constexpr int acc_form() {
-    return P == kFP32 ? kAccFx64 : (P == kBF16 ? kAccFx32 : kAccInt);
+    return W ? kAccF64 : (P == kFP32 ? kAccFx64 : (P == kBF16 ? kAccFx32 : kAccInt));
 }
 
 // Word 3 of a raw buffer descriptor on the gfx9 family (gfx950 included): no stride,
@@ -316,16 +312,16 @@ __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* ta
 // That saves HBM bytes but adds scalar work and a second chunk loop per item, so
 // it pays only where the kernel waits on HBM (the per-query kernel with fp32 or
 // bf16 weights), not where it is bound by instruction issue (shared traversal,
-// uint8 weights).
-template <int P, int TS, int CH, bool RB, bool DB>
+// uint8 weights). W: the wide-range pass (fp64 products w_q * w_d, fp64 sums).
+template <int P, int TS, int CH, bool DB, bool W = false>
 __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& qb, int32_t q0, int64_t tile, int ql,
                                            uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
                                            uint32_t* lds, TileShared& sh, int phase, SelState* state,
                                            unsigned long long* cand) {
     constexpr int BS = 512, NW = BS / kWave, TILE = 1 << TS, U = CH / kWave, GPT = TS - kGrainShift;
-    constexpr bool FX = P != kU8;                  // fixed-point products (fp32, bf16)
-    constexpr int AF = acc_form<P>();
-    constexpr int AW = AF == kAccFx64 ? 2 : 1;     // accumulator words per doc
+    constexpr bool FX = P != kU8;                  // fixed-point (or, W, fp64) products (fp32, bf16)
+    constexpr int AF = acc_form<P, W>();
+    constexpr int AW = (AF == kAccFx64 || AF == kAccF64) ? 2 : 1;  // accumulator words per doc
     unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(lds);  // [TILE] (fp32)
     uint32_t* acc32 = lds;                                                   // [TILE] (bf16, uint8)
     uint32_t* hist = lds + TILE * AW;                                        // [kHistBins]
@@ -335,6 +331,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     const int q = q0 + ql;
     if (qb.k[q] == 0) return;  // nothing is selected for it (also every padding slot of a batch)
     if (phase == 3 && state[ql].rescore != 1) return;  // only the queries that fell back
+    if (phase == 4 && state[ql].rescore != 2) return;  // only the wide-range queries
     const int64_t N = ix.n_docs;
     const int64_t base = tile << TS;
     const int tile_n = (int)min((int64_t)TILE, N - base);
@@ -377,7 +374,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         const int slot = dense ? before : nd + (t - before);
         bool zero_weight;
         if constexpr (FX) {
-            const double qd = qb.q_fx[qa + t];
+            const double qd = W ? (double)qb.q_w[qa + t] : qb.q_fx[qa + t];
             sh.seg_qd[slot] = qd;
             zero_weight = !(qd > 0.0);
         } else {
@@ -521,14 +518,21 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
                 const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    if (ok(u)) atomicAdd(at(acc, u), fx_prod<RB>(qd, k.w[u]));
+                    if (ok(u)) atomicAdd(at(acc, u), fx_product(qd, k.w[u]));
+            } else if constexpr (AF == kAccF64) {
+                // products of two fp32 values (or fp32 and bf16) are exact in fp64
+                double* acc = reinterpret_cast<double*>(DENSE ? acc64 : acc64f);
+                const double qd = uniform_f64(sh.seg_qd[k.seg]);
+#pragma unroll
+                for (int u = 0; u < U; u++)
+                    if (ok(u)) atomicAdd(at(acc, u), qd * (double)__uint_as_float(k.w[u]));
             } else if constexpr (AF == kAccFx32) {
                 // the query's scale keeps every doc's sum below 2^32 units
                 uint32_t* acc = DENSE ? acc32 : acc32f;
                 const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    if (ok(u)) atomicAdd(at(acc, u), (uint32_t)fx_prod<RB>(qd, k.w[u]));
+                    if (ok(u)) atomicAdd(at(acc, u), (uint32_t)fx_product(qd, k.w[u]));
             } else {
                 uint32_t* acc = DENSE ? acc32 : acc32f;
                 const uint32_t q8v = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.seg_q8[k.seg]);
@@ -587,7 +591,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // again and counts them then (bf16 has no phase 3 and counts here).
     const bool count = !(fused_q && P != kBF16);
     flush_tile<BS, AF>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
-                       FX ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins, app, app ? st->bound : 0ull, st,
+                       (FX && !W) ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins, app, app ? st->bound : 0ull, st,
                        cand + (int64_t)ql * kCandCap, write, count);
 }
 
@@ -595,7 +599,9 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
 // workgroups, so each query streams its own postings from HBM.
 // Both scoring kernels are held to 128 VGPRs (four wavefronts per SIMD): two
 // 512-thread workgroups per CU, which is what their LDS footprint allows.
-template <int P, int TS, int CH, bool RB>
+// Phases 3 and 4 (the listed queries' rows scored again) use one workgroup per tile
+// walking the list. W: the wide-range form (phase 4).
+template <int P, int TS, int CH, bool W = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_tiled(
     DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
     int phase, int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand,
@@ -603,17 +609,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ TileShared sh;
     const int64_t tile = phase_tile(phase, stride, (int64_t)blockIdx.x);
-    if (phase != 3) {
-        score_tile<P, TS, CH, RB, P != kU8>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state,
-                                             cand);
+    constexpr bool DB = P != kU8 && !W;
+    if (phase < 3) {
+        score_tile<P, TS, CH, DB, W>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state, cand);
         return;
     }
-    // rows of the queries that fell back from fused filtering (usually none): one
-    // workgroup per tile walks the list
+    // rows of the queries that fell back from fused filtering (phase 3) or were found
+    // wide range (phase 4); usually none. score_tile skips the other kind.
     const int nres = (int)counters[8];
     for (int r = 0; r < nres; r++) {
-        score_tile<P, TS, CH, RB, P != kU8>(ix, qb, q0, tile, rescore_list[r], S, ld, hist1, lds, sh, phase, state,
-                                             cand);
+        score_tile<P, TS, CH, DB, W>(ix, qb, q0, tile, rescore_list[r], S, ld, hist1, lds, sh, phase, state, cand);
         __syncthreads();
     }
 }
@@ -624,7 +629,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 // of a tile are its queries in the order given by `order` (heaviest first), so
 // every query of a tile runs on one XCD while the tile's postings are in its L2.
 // Every workgroup leaves the loop once its XCD's counter passes the item count.
-template <int P, int TS, int CH, bool RB>
+template <int P, int TS, int CH>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_persistent(
     DevIndex ix, DevBatch qb, int32_t q0, int32_t qt, const int32_t* __restrict__ order,
     uint32_t* __restrict__ counters, uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1, int phase,
@@ -646,7 +651,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (item >= items) break;
         const int64_t tile = phase_tile(phase, stride, x + 8 * (item / nq));
         const int ql = phase == 3 ? rescore_list[item % nq] : order[item % nq];
-        score_tile<P, TS, CH, RB, false>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh, phase, state, cand);
+        score_tile<P, TS, CH, false>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh, phase, state, cand);
         __syncthreads();
     }
 }
@@ -821,11 +826,6 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_copy16(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
 hipError_t fill_u32(void* p, int64_t n_words, hipStream_t s) { return launch_fill(p, n_words, 0u, s); }
 
 template <typename F>
@@ -838,7 +838,7 @@ hipError_t by_precision(int p, F f) {
     return hipErrorInvalidValue;
 }
 
-template <int P, int TS, int CH, bool RB>
+template <int P, int TS, int CH>
 hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, bool persistent,
                             const Workspace& ws, int64_t ld, hipStream_t s, int phase, int stride) {
     const int64_t n_tiles = phase_tiles(phase, stride, (ix.n_docs + (1 << TS) - 1) >> TS);
@@ -847,10 +847,10 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
     if (lds > 150 * 1024) return hipErrorInvalidValue;
     if (lds > 65536) {
         static const hipError_t attr = [&] {
-            hipError_t e = hipFuncSetAttribute((const void*)k_score_tiled<P, TS, CH, RB>,
+            hipError_t e = hipFuncSetAttribute((const void*)k_score_tiled<P, TS, CH>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e == hipSuccess)
-                e = hipFuncSetAttribute((const void*)k_score_persistent<P, TS, CH, RB>,
+                e = hipFuncSetAttribute((const void*)k_score_persistent<P, TS, CH>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             return e;
         }();
@@ -860,7 +860,7 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         }
     }
     if (!persistent) {
-        hipLaunchKernelGGL((k_score_tiled<P, TS, CH, RB>), dim3((unsigned)n_tiles, phase == 3 ? 1u : (unsigned)qt),
+        hipLaunchKernelGGL((k_score_tiled<P, TS, CH>), dim3((unsigned)n_tiles, phase == 3 ? 1u : (unsigned)qt),
                            dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand,
                            (const uint32_t*)ws.counters, (const int32_t*)ws.rescore_list);
         GS_CHECK_LAUNCH("k_score_tiled");
@@ -871,7 +871,7 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         int dev = 0, per_cu = 0;
         hipDeviceProp_t p{};
         if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_score_persistent<P, TS, CH, RB>, 512,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_score_persistent<P, TS, CH>, 512,
                                                          lds) != hipSuccess)
             return 0;
         return std::max(8, (p.multiProcessorCount * std::max(per_cu, 1)) / 8 * 8);
@@ -884,22 +884,22 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         const hipError_t e = launch_fill(ws.counters, 8, 0u, s);  // the first launch used the counters
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_score_persistent<P, TS, CH, RB>), dim3((unsigned)grid), dim3(512), lds, s, ix, qb, q0, qt,
+    hipLaunchKernelGGL((k_score_persistent<P, TS, CH>), dim3((unsigned)grid), dim3(512), lds, s, ix, qb, q0, qt,
                        (const int32_t*)ws.order, ws.counters, ws.scores, ld, ws.hist1, phase, stride, ws.state,
                        ws.cand, (const int32_t*)ws.rescore_list);
     GS_CHECK_LAUNCH("k_score_persistent");
     return hipSuccess;
 }
 
-template <int P, int TS, bool RB>
+template <int P, int TS>
 hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, bool persistent,
                        const Workspace& ws, int64_t ld, hipStream_t s, int phase, int stride) {
     switch (chunk) {
-        case 64: return launch_tiled_one<P, TS, 64, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
-        case 128: return launch_tiled_one<P, TS, 128, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
-        case 256: return launch_tiled_one<P, TS, 256, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
-        case 512: return launch_tiled_one<P, TS, 512, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
-        case 1024: return launch_tiled_one<P, TS, 1024, RB>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 64: return launch_tiled_one<P, TS, 64>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 128: return launch_tiled_one<P, TS, 128>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 256: return launch_tiled_one<P, TS, 256>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 512: return launch_tiled_one<P, TS, 512>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 1024: return launch_tiled_one<P, TS, 1024>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
     }
     return hipErrorInvalidValue;
 }
@@ -913,13 +913,6 @@ hipError_t launch_fill(void* p, int64_t n_words, uint32_t v, hipStream_t s) {
     const int64_t blocks = std::min<int64_t>((n_words + 255) / 256, 8192);
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n_words, v);
     GS_CHECK_LAUNCH("k_fill_u32");
-    return hipSuccess;
-}
-
-hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s) {
-    if (n16 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy16, dim3(4096), dim3(256), 0, s, (uint4*)dst, (const uint4*)src, n16);
-    GS_CHECK_LAUNCH("k_copy16");
     return hipSuccess;
 }
 
@@ -938,22 +931,42 @@ hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0
     return by_precision(ix.precision, [&](auto pc) -> hipError_t {
         constexpr int P = decltype(pc)::value;
         const bool persistent = o.kernel == 4;  // GS_KERNEL_SHARED: persistent, tile-major, XCD-aware
-        auto go = [&](auto rb) -> hipError_t {
-            constexpr bool RB = decltype(rb)::value;
-            switch (o.tile_shift) {
-                case 13: return tiled_chunk<P, 13, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
-                case 14: return tiled_chunk<P, 14, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
-                case 15:
-                    if constexpr (acc_form<P>() != kAccFx64)
-                        return tiled_chunk<P, 15, RB>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
-                    return hipErrorInvalidValue;  // 32768 64-bit accumulators exceed one CU's LDS
-            }
-            return hipErrorInvalidValue;
-        };
-        // fixed point: the raise of products that round to 0 units only where the batch needs it
-        if constexpr (P == kU8) return go(std::false_type());
-        else return o.raise ? go(std::true_type()) : go(std::false_type());
+        switch (o.tile_shift) {
+            case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
+            case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
+            case 15:
+                if constexpr (acc_form<P>() != kAccFx64)
+                    return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
+                return hipErrorInvalidValue;  // 32768 64-bit accumulators exceed one CU's LDS
+        }
+        return hipErrorInvalidValue;
     });
+}
+
+hipError_t launch_score_wide(const DevIndex& ix, const DevBatch& qb, int32_t q0, const Workspace& ws, hipStream_t s) {
+    // 8192 docs of fp64 accumulators (64 KiB of LDS), one workgroup per tile walking the list
+    constexpr int TS = 13, CH = 256;
+    const int64_t n_tiles = (ix.n_docs + (1 << TS) - 1) >> TS;
+    if (n_tiles <= 0) return hipSuccess;
+    const size_t lds = (size_t)((1 << TS) * 2 + kHistBins) * 4;
+    const int64_t ld = score_ld(ix.n_docs);
+    auto go = [&](auto pc) -> hipError_t {
+        constexpr int P = decltype(pc)::value;
+        static const hipError_t attr = hipFuncSetAttribute((const void*)k_score_tiled<P, TS, CH, true>,
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (attr != hipSuccess) {
+            g_failed_launch = "hipFuncSetAttribute(k_score_tiled, wide)";
+            return attr;
+        }
+        hipLaunchKernelGGL((k_score_tiled<P, TS, CH, true>), dim3((unsigned)n_tiles, 1u), dim3(512), lds, s, ix, qb,
+                           q0, ws.scores, ld, ws.hist1, 4, 1, ws.state, ws.cand, (const uint32_t*)ws.counters,
+                           (const int32_t*)ws.rescore_list);
+        GS_CHECK_LAUNCH("k_score_tiled (wide)");
+        return hipSuccess;
+    };
+    if (ix.precision == kFP32) return go(std::integral_constant<int, kFP32>());
+    if (ix.precision == kBF16) return go(std::integral_constant<int, kBF16>());
+    return hipSuccess;  // uint8 sums are exact
 }
 
 hipError_t launch_score_atomic(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const ScoreOpts& o,

@@ -37,6 +37,16 @@
 // refinement needed); such a query is listed, its other tiles are scored and
 // counted again, and a second k_select_first pass redoes its step 2 from the
 // complete histogram before steps 3 and 4.
+//
+// Wide-range check (fixed-point sums of the doc-tiled kernels, fp32 and bf16
+// weights): a fixed-point sum is within an absolute bound E of the exact score,
+// so a score far below the query's scale can miss the relative error budget. At
+// step 2 the lower edge of the k-th composite's bucket (a lower bound of the
+// k-th approximate score, also with fused filtering) is compared with the
+// query's limit (E over the budget). Below it, the query is listed as wide
+// range: every tile is scored again with fp64 accumulation of exact fp64
+// products (its histogram counted anew), and the second k_select_first pass
+// selects from those rows.
 #include "gs_internal.h"
 
 namespace gs {
@@ -90,22 +100,38 @@ __device__ __forceinline__ int64_t kq_of(const DevBatch& qb, int q, int64_t N) {
 // fell back, whose histograms are complete only then (phase 2 counts the seed tiles of a
 // fused fp32/uint8 query only).
 __global__ __launch_bounds__(64) void k_select_first(DevBatch qb, int32_t q0, int64_t N, int precision,
-                                                     const uint32_t* __restrict__ hist1, SelState* __restrict__ state,
+                                                     uint32_t* __restrict__ hist1, SelState* __restrict__ state,
                                                      uint32_t* __restrict__ counters, int32_t* __restrict__ rescore_list,
-                                                     int pass) {
+                                                     int pass, int wide_check) {
     const int ql = blockIdx.x, q = q0 + ql;
     SelState* st = state + ql;
-    if (pass == 1 && st->rescore != 1) return;
+    if (pass == 1 && st->rescore == 0) return;
     const int64_t kq = kq_of(qb, q, N);
     if (kq == 0) {
         if (threadIdx.x == 0) st->resolved = 2;
         return;
     }
-    const uint32_t* h = hist1 + (int64_t)ql * kHistBins;
+    uint32_t* h = hist1 + (int64_t)ql * kHistBins;
     uint32_t above;
     const int d = hist_walk(h, (uint32_t)kq, &above);
-    if (threadIdx.x != 0) return;
     const int fs = qb.first_shift[q];
+    if (pass == 0 && wide_check) {
+        // lower edge of the k-th composite's bucket: its score bits with the low ones cleared
+        const float s_lo = __uint_as_float((uint32_t)(((unsigned long long)d << fs) >> 32));
+        if ((double)s_lo < qb.q_wide_lim[q]) {
+            __syncthreads();  // every lane is done reading the histogram
+            for (int i = threadIdx.x; i < kHistBins; i += 64) h[i] = 0u;  // the fp64 pass counts anew
+            if (threadIdx.x == 0) {
+                st->fused = 0;
+                st->n_cand = 0;
+                st->resolved = 0;
+                st->rescore = 2;
+                rescore_list[atomicAdd(&counters[8], 1u)] = ql;
+            }
+            return;
+        }
+    }
+    if (threadIdx.x != 0) return;
     const int64_t ge = (int64_t)above + h[d];
     int64_t kept;  // composites at or above the filter threshold
     if (precision == kBF16 && d > 0 && ge + h[d - 1] <= kCandCap) {
@@ -505,21 +531,43 @@ __device__ void band_topk(const double* bs, const int32_t* bid, int nb, int64_t 
 
 // Band of the bf16 form. Every doc's approximate score satisfies
 //   s(1-delta) - E <= approx <= s(1+delta) + E
-// (delta: relative error of the stored bf16 weights and of the fp32 score; E:
-// the fixed-point error bound; a positive product never rounds to 0, so
-// approx = 0 exactly when s = 0). Then approx_k <= (1+delta) s_k + E, and every
-// true top-k doc has approx >= s(1-delta) - E >= (approx_k - E)(1-delta)/(1+delta) - E = tau.
-__device__ __forceinline__ double band_tau(float sk, float delta, double abs_err) {
-    const double d = (double)delta;
+// (delta: relative error of the stored bf16 weights and of the score's
+// arithmetic; E: the fixed-point error bound). Then approx_k <= (1+delta) s_k + E,
+// and every true top-k doc has
+// approx >= s(1-delta) - E >= (approx_k - E)(1-delta)/(1+delta) - E = tau.
+__device__ __forceinline__ double band_tau(float sk, double delta, double abs_err) {
+    const double d = delta;
     const double t = ((double)sk - abs_err) * (1.0 - d) / (1.0 + d) - abs_err;
     return t > 0.0 ? t * (1.0 - 1e-12) : 0.0;
+}
+
+// Error terms of the bf16 band for a query: relative (delta) and absolute (E).
+// Fixed-point sums: the stored-weight and final fp32 roundings, plus E. The fp64
+// pass (wide range): exact products, an fp64 sum (relative error below 1e-13 for
+// 256 terms) rounded once to fp32, no E. fp32 sums (global-atomic and
+// document-parallel kernels): each product and addition rounds, so delta also
+// covers gamma_m = m u / (1 - m u) with u = 2^-24 for m query terms; no E.
+__device__ __forceinline__ void band_error(const DevBatch& qb, int q, int acc, int rescore, int m, double* rel,
+                                           double* abs_err) {
+    const double d = (double)qb.delta[q];
+    if (rescore == 2) {
+        *rel = d + 1e-12;
+        *abs_err = 0.0;
+    } else if (acc == kAccFloat) {
+        const double mu = (double)(m + 1) * 0x1p-24;
+        *rel = (1.0 + d) * (1.0 + mu / (1.0 - mu)) - 1.0;
+        *abs_err = 0.0;
+    } else {
+        *rel = d;
+        *abs_err = qb.q_abs_err[q];
+    }
 }
 
 template <int P>
 __global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_t q0, SelState* __restrict__ state,
                                                 const unsigned long long* __restrict__ cand,
                                                 double* __restrict__ band_s, int32_t* __restrict__ band_id,
-                                                int32_t* __restrict__ out_ids, void* __restrict__ out_scores) {
+                                                int32_t* __restrict__ out_ids, void* __restrict__ out_scores, int acc) {
     __shared__ unsigned long long sel[kMaxK];
     __shared__ uint32_t hist[256];
     __shared__ int sh_d, sh_cnt;
@@ -632,16 +680,21 @@ __global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_
     }
     __syncthreads();
     const float sk = __uint_as_float((uint32_t)(sh_min >> 32));
+    double rel_err, abs_err;
+    band_error(qb, q, acc, st->rescore, nq, &rel_err, &abs_err);
     double* bs = band_s + (int64_t)ql * kCandCap;
     int32_t* bid = band_id + (int64_t)ql * kCandCap;
     int nb = 0;
     if (sk == 0.0f) {
         // fewer than k docs share a term with the query: the k winners are every doc with a
-        // positive score plus the lowest-id zero-score docs (a zero approximate score is exact)
+        // positive score plus the lowest-id zero-score docs. A zero approximate score is exact
+        // here: from fp32 or fp64 sums (no product of admissible weights underflows to 0), or
+        // from fixed point only if no positive product can round to 0 units (otherwise the
+        // wide-range check sent the query to the fp64 pass: its k-th bucket starts at 0).
         for (int i = tid; i < m; i += 1024) bid[i] = (int32_t)(~(uint32_t)sel[i]);
         nb = m;
     } else {
-            const double tau = band_tau(sk, qb.delta[q], qb.q_abs_err[q]);
+        const double tau = band_tau(sk, rel_err, abs_err);
         // with fused filtering the other tiles' candidates start at the bound, the seed tiles' at lo
         const unsigned long long lo = st->fused == 1 ? max(st->lo, st->bound) : st->lo;
         const double lo_val = (double)__uint_as_float((uint32_t)(lo >> 32));
@@ -745,11 +798,15 @@ __global__ void k_diag(int32_t q0, int32_t qt, const SelState* __restrict__ stat
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= qt) return;
     const SelState st = state[i];
-    int32_t* o = diag + (int64_t)(q0 + i) * 4;
+    int32_t* o = diag + (int64_t)(q0 + i) * kDiagWords;
     o[0] = st.n_cand;
     o[1] = st.passes;
     o[2] = st.band;
     o[3] = st.overflow;
+    o[4] = st.rescore;
+    o[5] = st.fused == 1 ? 1 : 0;
+    o[6] = 0;
+    o[7] = 0;
 }
 
 }  // namespace
@@ -770,34 +827,40 @@ hipError_t launch_seed_bound(const DevIndex& ix, const DevBatch& qb, int32_t q0,
 }
 
 hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, const Workspace& ws,
-                         int32_t* out_ids, void* out_scores, int32_t* diag, hipStream_t s, int tile_shift,
-                         int seed_stride, const std::function<hipError_t()>& after_first) {
+                         int32_t* out_ids, void* out_scores, int32_t* diag, hipStream_t s, int acc, int tile_shift,
+                         int seed_stride, const ScoreOpts* phase3, bool wide) {
     const int64_t N = ix.n_docs;
     const int per = 65536;
     const dim3 grid_scan((unsigned)((N + per - 1) / per), (unsigned)qt);
-    hipLaunchKernelGGL(k_select_first, dim3(qt), dim3(64), 0, s, qb, q0, N, ix.precision,
-                       (const uint32_t*)ws.hist1, ws.state, ws.counters, ws.rescore_list, 0);
+    const int wide_check = acc == kAccFixed ? 1 : 0;
+    hipLaunchKernelGGL(k_select_first, dim3(qt), dim3(64), 0, s, qb, q0, N, ix.precision, ws.hist1, ws.state,
+                       ws.counters, ws.rescore_list, 0, wide_check);
     GS_CHECK_LAUNCH("k_select_first");
-    if (after_first) {  // fused filtering: rows (and counts) for the queries that fell back
-        const hipError_t e = after_first();
+    if (phase3 || wide) {  // rows (and counts) of the listed queries: fused fallback, wide range
+        hipError_t e = hipSuccess;
+        if (phase3) e = launch_score_tiled(ix, qb, q0, qt, *phase3, ws, s, 3);
+        if (e == hipSuccess && wide) e = launch_score_wide(ix, qb, q0, ws, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_select_first, dim3(qt), dim3(64), 0, s, qb, q0, N, ix.precision,
-                           (const uint32_t*)ws.hist1, ws.state, ws.counters, ws.rescore_list, 1);
+        hipLaunchKernelGGL(k_select_first, dim3(qt), dim3(64), 0, s, qb, q0, N, ix.precision, ws.hist1, ws.state,
+                           ws.counters, ws.rescore_list, 1, 0);
         GS_CHECK_LAUNCH("k_select_first");
     }
     auto final_pass = [&]() -> hipError_t {
         switch (ix.precision) {
             case kFP32:
                 hipLaunchKernelGGL(k_final<kFP32>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
-                                   (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores);
+                                   (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores,
+                                   acc);
                 break;
             case kU8:
                 hipLaunchKernelGGL(k_final<kU8>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
-                                   (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores);
+                                   (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores,
+                                   acc);
                 break;
             default:
                 hipLaunchKernelGGL(k_final<kBF16>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
-                                   (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores);
+                                   (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores,
+                                   acc);
                 break;
         }
         GS_CHECK_LAUNCH("k_final");

@@ -85,10 +85,10 @@ def test_partial_update_pads_with_empty_queries(data):
         batch.update(q1, 100)  # 24 queries do not fit a capacity of 10
 
 
-def test_graph_replay_after_a_refill_that_needs_the_raise(data):
-    # fixed point: a positive product below one unit is raised to one unit; the kernels without
-    # that step serve batches in which no product can be that small. A graph captured on such a
-    # batch and replayed after a refill that needs the step must give the direct search's answer.
+def test_graph_replay_after_a_refill_with_tiny_products(data):
+    # fixed point: products of 1e-30 weights round to 0 units (far below the k-th scores, so the
+    # wide-range check leaves the queries alone). A graph captured on a batch without them and
+    # replayed after a refill with them must give the direct search's answer, bit for bit.
     gs, torch = _gs()
     docs, q1, q2 = data
     q1_terms = set(q1.terms.tolist())
