@@ -71,8 +71,11 @@ enum gs_precision {
 };
 
 enum gs_build_flags {
-    GS_KEEP_FORWARD = 1 /* keep the fp32 doc-major rows on the device (needed by the
-                           document-parallel kernel; always kept for GS_BF16) */
+    GS_KEEP_FORWARD = 1, /* keep the fp32 doc-major rows on the device (needed by the
+                            document-parallel kernel; always kept for GS_BF16) */
+    GS_KEEP_DOC_IDS = 2  /* keep 32-bit doc ids of every posting on the device (needed by
+                            the global-atomic kernel only: the doc-tiled kernels read
+                            16-bit or 8-bit ids, so by default they are not uploaded) */
 };
 
 /* Scoring kernels (Sec. 5.2 term-parallel scatter-add; Sec. 5.3 document-parallel). */
@@ -147,7 +150,8 @@ const char* gs_last_error(void);
  *
  * Layout built (all device-resident, owned by the index):
  *  - posting lists term-major, each sorted by doc id (Sec. 3.2), padded with
- *    (doc -1, weight 0) entries to a multiple of 64 (one wavefront);
+ *    (doc -1, weight 0) entries to a multiple of 64 (one wavefront); their
+ *    32-bit doc ids only with GS_KEEP_DOC_IDS;
  *  - term_off[V+1] (int64) list starts, term_len[V] real lengths;
  *  - per 64-posting block: the largest weight and the first doc id;
  *  - per term and per tile of tile_grain docs: the offset of the first
@@ -164,6 +168,9 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
                        const float* weights, int64_t nnz, int32_t vocab_size, int32_t precision,
                        uint32_t flags, void* hip_stream, gs_index* out);
 
+/* Sizes of a built index (Sec. 3.2 arrays; device memory as in Sec. 3.3's
+ * memory model plus the segment table and block metadata). out (host,
+ * caller-owned) receives them. Errors: GS_EINVAL (null argument). */
 int32_t gs_index_info(gs_index index, gs_index_info_t* out);
 
 /*
@@ -175,6 +182,8 @@ int32_t gs_index_info(gs_index index, gs_index_info_t* out);
  * the index's).
  */
 int32_t gs_index_dense_terms(gs_index index, uint8_t* out, int32_t vocab_size);
+/* Releases the index's device memory (the resident index of Sec. 3.2). NULL is a
+ * no-op. Batches created for it may still be freed afterwards, not searched. */
 void gs_free_index(gs_index index);
 
 /*
@@ -258,6 +267,20 @@ int32_t gs_batch_update(gs_batch batch, const int64_t* q_row_ptr, int32_t n_quer
                         const int32_t* k, void* hip_stream);
 
 /*
+ * Device workspace (bytes) for a search of a batch of n_queries queries with
+ * q_nnz terms in total and k <= k_max: one score array of n_docs 32-bit words
+ * per live query (Sec. 4.2's per-query accumulators) plus selection scratch,
+ * for all n_queries at once, or for opts->query_tile of them when that is set
+ * (opts may be NULL). A smaller workspace still works down to
+ * gs_workspace_size(index, 1, opts): queries then run in tiles (score arrays
+ * tiled to fit memory). Errors: GS_EINVAL (negative sizes, k_max outside
+ * [0, GS_MAX_K], q_nnz above n_queries x GS_MAX_QUERY_NNZ, bad opts),
+ * GS_EUNSUPPORTED (as gs_search_batch).
+ */
+int32_t gs_search_workspace_size(gs_index index, int32_t n_queries, int64_t q_nnz, int32_t k_max,
+                                 const gs_search_opts* opts, size_t* bytes);
+
+/*
  * Device workspace (bytes) needed to search query_tile queries at once with
  * these options (opts may be NULL). It holds one score array of n_docs 32-bit
  * words per live query plus selection scratch.
@@ -266,7 +289,9 @@ int32_t gs_workspace_size(gs_index index, int32_t query_tile, const gs_search_op
                           size_t* bytes);
 
 /*
- * Search a prepared batch: exact top-k per query.
+ * Search a prepared batch: exact top-k per query. Scores are the inner product
+ * of Sec. 2.1 over the query's terms, accumulated per query as in Sec. 4.1
+ * (second eq.) and Sec. 4.2; the top-k is exact (Sec. 4.3).
  * workspace: device, workspace_bytes >= gs_workspace_size(index, 1, opts);
  *   queries are processed in tiles of as many as the workspace holds
  *   (score arrays tiled to fit memory).
@@ -283,7 +308,8 @@ int32_t gs_search_batch(gs_index index, gs_batch batch, void* workspace, size_t 
                         void* hip_stream);
 
 /*
- * Convenience form: gs_batch_create + gs_search_batch + gs_batch_free.
+ * Convenience form (the search of Sec. 4.2 from a host CSR of queries):
+ * gs_batch_create + gs_search_batch + gs_batch_free.
  * Synchronous (the stream is synchronised before returning). Returns
  * GS_ECAPACITY when the fp64-rescored error band of some query (GS_BF16) held
  * more than 32768 documents: that query's row is then padding (see
@@ -395,14 +421,17 @@ int32_t gs_lds_atomic_probe(int32_t op, int32_t pattern, int32_t workgroups, int
 /*
  * Continuous-batching request loop over one resident index (the paper lists
  * streaming query batching for serving as future work (3), Sec. 8).
- * Requests queue as they arrive. A scheduler thread owns n_slots device slots,
- * each with its own HIP stream, a reusable batch of max_batch queries, a
- * workspace holding one score array per query and pinned result rows.
- * Whenever a slot is free it takes up to max_batch waiting requests (oldest
- * first) and runs their search while other slots keep running, so requests
- * that arrive while others are on the GPU join as slots free up. Admission is
- * by memory: with memory_budget > 0, n_slots is reduced so that all slots'
- * workspaces (n_docs x 4 B per query plus selection scratch) fit the budget.
+ * Requests queue as they arrive. Admission is by memory: the server holds one
+ * workspace arena of query rows (a row: the n_docs x 4 B score array of one
+ * query plus its selection scratch, the memory a query's score buffer needs),
+ * as many rows as memory_budget allows (without a budget, n_slots x max_batch).
+ * A scheduler thread owns n_slots slots, each with its own HIP stream, a
+ * reusable batch of max_batch queries and pinned result rows. Whenever a slot
+ * is free and requests wait, it takes a contiguous run of free rows and as many
+ * waiting requests (oldest first, at most max_batch) and runs their search while
+ * other slots keep running; the rows return to the arena when the step ends. So
+ * requests that arrive while others are on the GPU are admitted as slots and
+ * memory free up, and at most arena_rows queries are on the device at once.
  * Results are identical to a search of the same query alone (the integer and
  * fixed-point sums do not depend on the batch).
  */
@@ -413,44 +442,55 @@ typedef struct gs_server_opts {
     int32_t n_slots;       /* concurrent device steps (streams) */
     int32_t k_max;         /* largest k a request may ask for (<= GS_MAX_K) */
     int32_t reserved;      /* must be 0 */
-    int64_t memory_budget; /* device bytes for all slots' workspaces (0: no limit) */
+    int64_t memory_budget; /* device bytes for the in-flight queries' rows (0: n_slots x max_batch rows) */
     gs_search_opts search; /* kernel options used for every step */
 } gs_server_opts;
 
 typedef struct gs_server_stats_t {
     int32_t n_slots;
     int32_t max_batch;
-    int64_t completed;     /* requests finished */
+    int64_t completed;     /* requests finished with results */
+    int64_t failed;        /* requests finished with an error status */
     int64_t device_steps;  /* searches run */
     double mean_batch;     /* requests per search */
-    int64_t max_in_flight; /* most requests on the device at once */
-    int64_t pending;       /* requests waiting for a slot now */
-    int64_t slot_bytes;    /* workspace bytes of one slot */
+    int64_t max_in_flight; /* most requests on the device at once (at most arena_rows) */
+    int64_t pending;       /* requests waiting for a slot or rows now */
+    int64_t arena_rows;    /* queries whose rows fit the budget at once */
+    int64_t arena_bytes;   /* device bytes of the arena */
+    int64_t row_bytes;     /* arena bytes per query row */
 } gs_server_stats_t;
 
-/* Allocates every slot up front (device and pinned memory) and starts the
- * scheduler. Errors: GS_EINVAL, GS_ECAPACITY (budget below one slot),
- * GS_ENOMEM, GS_EHIP. */
+/* Allocates the arena and every slot up front (device and pinned memory) and
+ * starts the scheduler. Errors: GS_EINVAL, GS_ECAPACITY (budget below one
+ * query's row), GS_ENOMEM, GS_EHIP. */
 int32_t gs_server_create(gs_index index, const gs_server_opts* opts, gs_server* out);
 
 /* Queue one query (host arrays, copied). Returns a ticket >= 0, or a negative
  * gs_status (GS_EINVAL: bad term, weight, duplicate, nnz > GS_MAX_QUERY_NNZ,
- * k outside [0, k_max]). Thread-safe. */
+ * k outside [0, k_max], server stopping). Thread-safe. */
 int64_t gs_server_submit(gs_server server, const int32_t* term_ids, const float* weights, int32_t nnz,
                          int32_t k);
 
 /* Wait for a ticket (timeout_ms < 0: no limit), then copy its k ids and scores
- * (float, double for GS_BF16, int32 for GS_U8) to host memory and give its
- * latency from submission to completion in ms. Each ticket can be collected
- * once. Thread-safe. Errors: GS_EINVAL (unknown or already collected ticket),
- * GS_ETIMEOUT, or the status of a failed search. */
+ * (host, caller-owned: k int32 ids; k floats, doubles for GS_BF16, int32 for
+ * GS_U8) and give its latency from submission to completion in ms (any output
+ * may be NULL). Each ticket is collected once. Thread-safe. Errors: GS_EINVAL
+ * (unknown ticket, already collected, or the server was destroyed first),
+ * GS_ETIMEOUT (not finished in time; the ticket stays collectable), or the
+ * status of its failed search (GS_ECAPACITY: a bf16 band overflow). */
 int32_t gs_server_wait(gs_server server, int64_t ticket, int32_t timeout_ms, int32_t* out_ids,
                        void* out_scores, double* latency_ms);
+
+/* Non-blocking form of gs_server_wait: GS_OK and the result if the request has
+ * finished, GS_ETIMEOUT if it has not (the ticket stays collectable). */
+int32_t gs_server_poll(gs_server server, int64_t ticket, int32_t* out_ids, void* out_scores,
+                       double* latency_ms);
 
 int32_t gs_server_stats(gs_server server, gs_server_stats_t* out);
 
 /* Stops the scheduler after the steps on the device finish; requests still
- * waiting for a slot are dropped. Call after every gs_server_wait has returned. */
+ * waiting for a slot are dropped, and callers blocked in gs_server_wait return
+ * GS_EINVAL before the server is freed. */
 void gs_server_destroy(gs_server server);
 
 #ifdef __cplusplus

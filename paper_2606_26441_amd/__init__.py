@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libgpusparse.so")
 
 GS_OK, GS_EINVAL, GS_ENOMEM, GS_EHIP, GS_ECAPACITY, GS_EUNSUPPORTED, GS_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 GS_FP32, GS_BF16, GS_U8 = 0, 1, 2
-GS_KEEP_FORWARD = 1
+GS_KEEP_FORWARD, GS_KEEP_DOC_IDS = 1, 2
 GS_KERNEL_AUTO, GS_KERNEL_TILED, GS_KERNEL_ATOMIC, GS_KERNEL_DOCPAR, GS_KERNEL_SHARED = 0, 1, 2, 3, 4
 GS_MAX_K = 4096
 GS_MAX_QUERY_NNZ = 256
@@ -54,8 +54,9 @@ class ServerOpts(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("completed", ctypes.c_int64),
-                ("device_steps", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("max_in_flight", ctypes.c_int64),
-                ("pending", ctypes.c_int64), ("slot_bytes", ctypes.c_int64)]
+                ("failed", ctypes.c_int64), ("device_steps", ctypes.c_int64), ("mean_batch", ctypes.c_double),
+                ("max_in_flight", ctypes.c_int64), ("pending", ctypes.c_int64), ("arena_rows", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_int64), ("row_bytes", ctypes.c_int64)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -109,10 +110,14 @@ def _load() -> ctypes.CDLL:
     lib.gs_server_submit.restype = i64
     lib.gs_server_wait.argtypes = [vp, i64, i32, vp, vp, P(ctypes.c_double)]
     lib.gs_server_wait.restype = i32
+    lib.gs_server_poll.argtypes = [vp, i64, vp, vp, P(ctypes.c_double)]
+    lib.gs_server_poll.restype = i32
     lib.gs_server_stats.argtypes = [vp, P(ServerStats)]
     lib.gs_server_stats.restype = i32
     lib.gs_server_destroy.argtypes = [vp]
     lib.gs_server_destroy.restype = None
+    lib.gs_search_workspace_size.argtypes = [vp, i32, i64, i32, P(SearchOpts), P(sz)]
+    lib.gs_search_workspace_size.restype = i32
     lib.gs_workspace_size.argtypes = [vp, i32, P(SearchOpts), P(sz)]
     lib.gs_workspace_size.restype = i32
     lib.gs_search_batch.argtypes = [vp, vp, vp, sz, vp, vp, P(SearchOpts), vp]
@@ -133,7 +138,6 @@ def _load() -> ctypes.CDLL:
 
 
 lib = _load()
-_TUNED = {}  # (n_docs, precision, n_queries) -> (best SearchOpts, timing table)
 
 
 def _check(rc: int, where: str):
@@ -194,19 +198,21 @@ class Index:
     """GPU-resident inverted index built from a doc-major CSR (row_ptr, terms, weights)."""
 
     def __init__(self, row_ptr, terms, weights, vocab: int, precision="fp32", keep_forward: bool = False,
-                 stream=None):
+                 stream=None, keep_doc_ids: bool = False):
         rp, t, w = _np(row_ptr, np.int64), _np(terms, np.int32), _np(weights, np.float32)
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        flags = GS_KEEP_FORWARD if keep_forward else 0
+        flags = (GS_KEEP_FORWARD if keep_forward else 0) | (GS_KEEP_DOC_IDS if keep_doc_ids else 0)
         h = ctypes.c_void_p()
         _check(lib.gs_build_index(rp.ctypes.data, rp.shape[0] - 1, t.ctypes.data, w.ctypes.data, t.shape[0], vocab,
                                   self.precision, flags, _stream_ptr(stream), ctypes.byref(h)), "gs_build_index")
         self._h = h
         self.vocab = vocab
+        self._tuned = {}  # autotuner choices: (index handle, batch capacity, k_max) -> (best, table)
 
     @classmethod
-    def from_rows(cls, rows, precision="fp32", keep_forward=False, stream=None):
-        return cls(rows.row_ptr, rows.terms, rows.weights, rows.vocab, precision, keep_forward, stream)
+    def from_rows(cls, rows, precision="fp32", keep_forward=False, stream=None, keep_doc_ids=False):
+        return cls(rows.row_ptr, rows.terms, rows.weights, rows.vocab, precision, keep_forward, stream,
+                   keep_doc_ids)
 
     @property
     def handle(self):
@@ -234,6 +240,13 @@ class Index:
                                      ctypes.byref(n)), "gs_workspace_size")
         return int(n.value)
 
+    def search_workspace_bytes(self, n_queries: int, q_nnz: int, k_max: int, opts: Optional[SearchOpts] = None) -> int:
+        n = ctypes.c_size_t(0)
+        _check(lib.gs_search_workspace_size(self._h, int(n_queries), int(q_nnz), int(k_max),
+                                            ctypes.byref(opts) if opts else None, ctypes.byref(n)),
+               "gs_search_workspace_size")
+        return int(n.value)
+
     def workspace(self, query_tile: int, opts: Optional[SearchOpts] = None, device="cuda") -> torch.Tensor:
         return torch.empty(self.workspace_bytes(query_tile, opts), dtype=torch.uint8, device=device)
 
@@ -243,7 +256,8 @@ class Index:
     def search(self, batch: "Batch", workspace: Optional[torch.Tensor] = None, opts: Optional[SearchOpts] = None,
                out=None, stream=None):
         """Exact top-k of a prepared batch. Returns (ids [n, k_max] int32, scores [n, k_max]) on the device."""
-        if workspace is None:
+        own_ws = workspace is None
+        if own_ws:
             workspace = self.workspace(max(1, min(batch.n_queries, 64)), opts)
         if out is None:
             ids = torch.empty((batch.n_queries, batch.k_max), dtype=torch.int32, device=workspace.device)
@@ -254,6 +268,9 @@ class Index:
         _check(lib.gs_search_batch(self._h, batch.handle, workspace.data_ptr(), workspace.numel(), ids.data_ptr(),
                                    scores.data_ptr(), ctypes.byref(opts) if opts else None, _stream_ptr(stream)),
                "gs_search_batch")
+        if own_ws and stream is not None:
+            # the implicit workspace is freed on return while the search may still run on `stream`
+            workspace.record_stream(stream)
         return ids, scores
 
     def search_host(self, queries, k, k_max: Optional[int] = None, workspace: Optional[torch.Tensor] = None,
@@ -272,14 +289,16 @@ class Index:
                              ctypes.byref(opts) if opts else None, _stream_ptr(stream)), "gs_search")
         return ids, scores
 
-    def autotune(self, batch: "Batch", workspace: Optional[torch.Tensor] = None, reps: int = 2, stream=None):
-        """Time every candidate option set on this batch; returns (best SearchOpts, [(opts dict, ms), ...]).
+    def autotune(self, batch: "Batch", workspace: Optional[torch.Tensor] = None, reps: int = 2, stream=None,
+                 cache: bool = True, return_outputs: bool = False):
+        """Time every candidate option set on this batch; returns (best SearchOpts, [(opts dict, ms), ...]),
+        plus (ids, scores) as numpy arrays (the best option set's result) with return_outputs.
 
-        Results are cached per (collection size, precision, batch size) for the life of the process.
+        With cache, the choice is kept per (index, batch capacity, k_max) for the life of the index.
         """
-        key = (self.n_docs, self.precision, batch.n_queries)
-        if key in _TUNED:
-            return _TUNED[key]
+        key = (self._h.value, batch.n_queries, batch.k_max)
+        if cache and not return_outputs and key in self._tuned:
+            return self._tuned[key]
         if workspace is None:
             workspace = self.workspace(batch.n_queries)
         ids = torch.empty((batch.n_queries, batch.k_max), dtype=torch.int32, device=workspace.device)
@@ -293,8 +312,11 @@ class Index:
                                ctypes.byref(n)), "gs_autotune")
         table = [({"kernel": cands[i].kernel, "tile_docs": cands[i].tile_docs, "chunk": cands[i].chunk},
                   float(times[i])) for i in range(min(n.value, 64))]
-        _TUNED[key] = (best, table)
-        return best, table
+        if cache:
+            self._tuned[key] = (best, table)
+        if return_outputs:
+            return best, table, (ids.cpu().numpy(), sc.cpu().numpy())
+        return self._tuned[key] if cache else (best, table)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -398,7 +420,7 @@ class Graph:
 
 
 class Server:
-    """Continuous-batching request loop (gs_server_*) over a resident index."""
+    """Continuous-batching request loop (gs_server_*) over a resident index; admission by memory_budget."""
 
     def __init__(self, index: Index, max_batch: int = 32, n_slots: int = 4, k_max: int = 1000, memory_budget: int = 0,
                  opts: Optional[SearchOpts] = None):
@@ -426,6 +448,17 @@ class Server:
         lat = ctypes.c_double(0)
         _check(lib.gs_server_wait(self._h, int(ticket), int(timeout_ms), ids.ctypes.data, sc.ctypes.data,
                                   ctypes.byref(lat)), "gs_server_wait")
+        return ids[:k], sc[:k], lat.value
+
+    def poll(self, ticket: int, k: int):
+        """(ids, scores, latency ms) if the query has finished, else None (gs_server_poll)."""
+        ids = np.empty(max(k, 1), np.int32)
+        sc = np.empty(max(k, 1), self.score_dtype)
+        lat = ctypes.c_double(0)
+        rc = lib.gs_server_poll(self._h, int(ticket), ids.ctypes.data, sc.ctypes.data, ctypes.byref(lat))
+        if rc == GS_ETIMEOUT:
+            return None
+        _check(rc, "gs_server_poll")
         return ids[:k], sc[:k], lat.value
 
     def stats(self) -> dict:

@@ -519,27 +519,31 @@ struct SpanRecorder {
 
 namespace gs {
 
-size_t workspace_bytes(int64_t n_docs, int32_t qt, int32_t precision) {
-    const size_t ld = (size_t)((n_docs + 63) / 64 * 64);
+// Workspace of `rows` query rows. Every per-query array is indexed by row, so a search of n
+// queries may run on rows [r0, r0 + n) of a larger workspace (the server's arena): the
+// work-prefix array of the global-atomic kernel takes kMaxQueryNnz + 1 entries per row for
+// that reason. One block of step counters follows (a search on rows of an arena brings its own).
+size_t arena_bytes(int64_t n_docs, int64_t rows, int32_t precision) {
+    const size_t ld = (size_t)((n_docs + 63) / 64 * 64), R = (size_t)rows;
     size_t b = 0;
-    b += align256((size_t)qt * ld * 4);
-    b += 2 * align256((size_t)qt * kHistBins * 4);
-    b += align256((size_t)qt * sizeof(SelState));
-    b += align256((size_t)qt * kCandCap * 8);
+    b += align256(R * ld * 4);
+    b += 2 * align256(R * kHistBins * 4);
+    b += align256(R * sizeof(SelState));
+    b += align256(R * kCandCap * 8);
     if (precision == kBF16) {
-        b += align256((size_t)qt * kCandCap * 8);
-        b += align256((size_t)qt * kCandCap * 4);
+        b += align256(R * kCandCap * 8);
+        b += align256(R * kCandCap * 4);
     }
-    b += align256(((size_t)qt * kMaxQueryNnz + 1) * 8);
-    b += align256((size_t)qt * kMaxQueryNnz * 4);
-    b += align256((size_t)qt * 4);
+    b += align256(R * (kMaxQueryNnz + 1) * 8);
+    b += align256(R * kMaxQueryNnz * 4);
+    b += align256(R * 4);
     b += align256(16 * 4);
-    b += align256((size_t)qt * 4);
+    b += align256(R * 4);
     return b;
 }
 
-void carve_workspace(void* base, int64_t n_docs, int32_t qt, int32_t precision, Workspace* ws) {
-    const size_t ld = (size_t)((n_docs + 63) / 64 * 64);
+void carve_rows(void* base, int64_t n_docs, int64_t rows, int32_t precision, int64_t r0, Workspace* ws) {
+    const size_t ld = (size_t)((n_docs + 63) / 64 * 64), R = (size_t)rows, o = (size_t)r0;
     char* p = (char*)base;
     auto take = [&](size_t n) {
         char* r = p;
@@ -547,22 +551,28 @@ void carve_workspace(void* base, int64_t n_docs, int32_t qt, int32_t precision, 
         return r;
     };
     ws->ld = (int64_t)ld;
-    ws->scores = (uint32_t*)take((size_t)qt * ld * 4);
-    ws->hist1 = (uint32_t*)take((size_t)qt * kHistBins * 4);
-    ws->hist_ref = (uint32_t*)take((size_t)qt * kHistBins * 4);
-    ws->state = (SelState*)take((size_t)qt * sizeof(SelState));
-    ws->cand = (unsigned long long*)take((size_t)qt * kCandCap * 8);
+    ws->scores = (uint32_t*)take(R * ld * 4) + o * ld;
+    ws->hist1 = (uint32_t*)take(R * kHistBins * 4) + o * kHistBins;
+    ws->hist_ref = (uint32_t*)take(R * kHistBins * 4) + o * kHistBins;
+    ws->state = (SelState*)take(R * sizeof(SelState)) + o;
+    ws->cand = (unsigned long long*)take(R * kCandCap * 8) + o * kCandCap;
     ws->band_s = nullptr;
     ws->band_id = nullptr;
     if (precision == kBF16) {
-        ws->band_s = (double*)take((size_t)qt * kCandCap * 8);
-        ws->band_id = (int32_t*)take((size_t)qt * kCandCap * 4);
+        ws->band_s = (double*)take(R * kCandCap * 8) + o * kCandCap;
+        ws->band_id = (int32_t*)take(R * kCandCap * 4) + o * kCandCap;
     }
-    ws->work_prefix = (int64_t*)take(((size_t)qt * kMaxQueryNnz + 1) * 8);
-    ws->work_pair_q = (int32_t*)take((size_t)qt * kMaxQueryNnz * 4);
-    ws->order = (int32_t*)take((size_t)qt * 4);
+    ws->work_prefix = (int64_t*)take(R * (kMaxQueryNnz + 1) * 8) + o * (kMaxQueryNnz + 1);
+    ws->work_pair_q = (int32_t*)take(R * kMaxQueryNnz * 4) + o * kMaxQueryNnz;
+    ws->order = (int32_t*)take(R * 4) + o;
     ws->counters = (uint32_t*)take(16 * 4);
-    ws->rescore_list = (int32_t*)take((size_t)qt * 4);
+    ws->rescore_list = (int32_t*)take(R * 4) + o;
+}
+
+size_t workspace_bytes(int64_t n_docs, int32_t qt, int32_t precision) { return arena_bytes(n_docs, qt, precision); }
+
+void carve_workspace(void* base, int64_t n_docs, int32_t qt, int32_t precision, Workspace* ws) {
+    carve_rows(base, n_docs, qt, precision, 0, ws);
 }
 
 }  // namespace gs
@@ -654,7 +664,7 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     *out = nullptr;
     if (vocab_size < 1) return fail(GS_EINVAL, "vocab_size < 1");
     if (precision < kFP32 || precision > kU8) return fail(GS_EINVAL, "unknown precision");
-    if (flags & ~(uint32_t)GS_KEEP_FORWARD) return fail(GS_EINVAL, "unknown flag");
+    if (flags & ~(uint32_t)(GS_KEEP_FORWARD | GS_KEEP_DOC_IDS)) return fail(GS_EINVAL, "unknown flag");
     if (n_docs >= (int64_t)1 << 31) return fail(GS_EINVAL, "n_docs must be < 2^31");
     Rows r{row_ptr, term_ids, weights, n_docs, {}, {}};
     int32_t rc = check_rows(r, nnz, vocab_size, vocab_size, "documents");
@@ -704,7 +714,10 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     int32_t *term_len = nullptr, *post_doc = nullptr, *tile_off = nullptr;
     if ((rc = dev_upload(ix->allocs, ix->bytes, L.term_off.data(), L.term_off.size(), &term_off, s))) return done(rc);
     if ((rc = dev_upload(ix->allocs, ix->bytes, L.term_len.data(), L.term_len.size(), &term_len, s))) return done(rc);
-    if ((rc = dev_upload(ix->allocs, ix->bytes, L.post_doc.data(), L.post_doc.size(), &post_doc, s))) return done(rc);
+    // 32-bit doc ids only for the global-atomic kernel: the doc-tiled kernels read 16- or 8-bit ones
+    if (flags & GS_KEEP_DOC_IDS)
+        if ((rc = dev_upload(ix->allocs, ix->bytes, L.post_doc.data(), L.post_doc.size(), &post_doc, s)))
+            return done(rc);
     if ((rc = dev_upload(ix->allocs, ix->bytes, L.tile_off.data(), L.tile_off.size(), &tile_off, s))) return done(rc);
     d.term_off = term_off;
     d.term_len = term_len;
@@ -729,6 +742,9 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
         for (auto& x : th) x.join();
         if ((rc = dev_upload(ix->allocs, ix->bytes, low.data(), low.size(), &lo, s, kPostSlack))) return done(rc);
         d.post_lo = lo;
+        // the upload is asynchronous: `low` must outlive it
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return done(fail(GS_EHIP, std::string("upload: ") + hipGetErrorString(e)));
     }
     if (precision == kFP32) {
         float* p = nullptr;
@@ -749,6 +765,7 @@ int32_t gs_build_index(const int64_t* row_ptr, int64_t n_docs, const int32_t* te
     if ((rc = dev_upload(ix->allocs, ix->bytes, L.blk_first.data(), L.blk_first.size(), &blk_first, s)))
         return done(rc);
     d.blk_first = blk_first;
+    d.blk_max = blk_max;
     {
         // Byte form of the doc ids: a term whose every 64-posting block spans at most 256 docs
         // stores each id as its distance to the block's first doc.
@@ -1022,6 +1039,8 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
     if (o->kernel != GS_KERNEL_AUTO) so->kernel = o->kernel;
     if (so->kernel == GS_KERNEL_DOCPAR && !(ix->flags & GS_KEEP_FORWARD))
         return fail(GS_EUNSUPPORTED, "document-parallel kernel needs an index built with GS_KEEP_FORWARD");
+    if (so->kernel == GS_KERNEL_ATOMIC && !(ix->flags & GS_KEEP_DOC_IDS))
+        return fail(GS_EUNSUPPORTED, "global-atomic kernel needs an index built with GS_KEEP_DOC_IDS");
     if (o->query_tile < 0) return fail(GS_EINVAL, "query_tile < 0");
     switch (o->tile_docs) {
         case 0: break;
@@ -1037,6 +1056,22 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
         case 64: case 128: case 256: case 512: case 1024: so->chunk = o->chunk; break;
         default: return fail(GS_EINVAL, "chunk must be 0, 64, 128, 256, 512 or 1024");
     }
+    return GS_OK;
+}
+
+int32_t gs_search_workspace_size(gs_index ix, int32_t n_queries, int64_t q_nnz, int32_t k_max,
+                                 const gs_search_opts* opts, size_t* bytes) {
+    g_err.clear();
+    if (!ix || !bytes) return fail(GS_EINVAL, "null argument");
+    if (n_queries < 0 || q_nnz < 0 || q_nnz > (int64_t)n_queries * kMaxQueryNnz)
+        return fail(GS_EINVAL, "n_queries < 0, or q_nnz outside [0, n_queries * GS_MAX_QUERY_NNZ]");
+    if (k_max < 0 || k_max > GS_MAX_K) return fail(GS_EINVAL, "k_max outside [0, GS_MAX_K]");
+    ScoreOpts so;
+    int32_t rc = resolve_opts(ix, opts, &so);
+    if (rc != GS_OK) return rc;
+    int32_t live = std::max(n_queries, 1);
+    if (opts && opts->query_tile > 0) live = std::min(live, opts->query_tile);
+    *bytes = workspace_bytes(ix->n_docs, live, ix->precision);
     return GS_OK;
 }
 
@@ -1062,6 +1097,7 @@ int32_t plan_search(gs_index ix, gs_batch b, size_t workspace_bytes_, const gs_s
     if (b->index != ix) return fail(GS_EINVAL, "batch was created for another index");
     int32_t rc = resolve_opts(ix, opts, so);
     if (rc != GS_OK) return rc;
+    if ((!opts || opts->kernel == GS_KERNEL_AUTO) && b->n_active >= 32) so->kernel = GS_KERNEL_SHARED;
     if (workspace_bytes(ix->n_docs, 1, ix->precision) > workspace_bytes_)
         return fail(GS_ECAPACITY, "workspace smaller than gs_workspace_size(index, 1)");
     const int32_t nq = std::max(b->n_queries, 1);
@@ -1079,7 +1115,7 @@ int32_t plan_search(gs_index ix, gs_batch b, size_t workspace_bytes_, const gs_s
 // Queries [0, nq) are searched; output rows [nq, capacity) are written as padding
 // (id -1, score 0). A direct search passes the queries of the last update, a
 // graph the whole capacity (it is replayed after updates of any size).
-int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int32_t qt, const ScoreOpts& so_in,
+int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, const Workspace& ws, int32_t qt, const ScoreOpts& so_in,
                        int32_t* out_ids, void* out_scores, hipStream_t s, bool timing) {
     ScoreOpts so = so_in;
     // Fused candidate filtering (doc-tiled kernels): every stride-th tile seeds a lower bound
@@ -1094,8 +1130,6 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int
         if (!tiled || so.seed_stride == 0 || n_tiles < 2 * (int64_t)stride || nq < 32) stride = 0;
         so.seed_stride = stride;
     }
-    Workspace ws;
-    carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
     (void)hipGetLastError();  // launches below report their own status; drop any earlier, unrelated one
     g_failed_launch = "";
     for (int32_t q0 = 0; q0 < nq; q0 += qt) {
@@ -1157,6 +1191,30 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, void* workspace, int
 
 }  // namespace
 
+namespace gs {
+
+int32_t search_rows(gs_index ix, gs_batch b, void* arena, int64_t rows, int64_t r0, uint32_t* counters,
+                    const gs_search_opts* opts, int32_t* out_ids, void* out_scores, hipStream_t s) {
+    if (!ix || !b || !arena || !counters) return fail(GS_EINVAL, "null argument");
+    if (b->index != ix) return fail(GS_EINVAL, "batch was created for another index");
+    const int32_t n = b->n_active;
+    if (r0 < 0 || r0 + n > rows) return fail(GS_EINVAL, "rows outside the arena");
+    ScoreOpts so;
+    int32_t rc = resolve_opts(ix, opts, &so);
+    if (rc != GS_OK) return rc;
+    if ((!opts || opts->kernel == GS_KERNEL_AUTO) && n >= 32) so.kernel = GS_KERNEL_SHARED;
+    if (b->n_queries == 0 || b->k_max == 0 || n == 0) return GS_OK;
+    DeviceGuard g(ix->device);
+    Workspace ws;
+    carve_rows(arena, ix->n_docs, rows, ix->precision, r0, &ws);
+    ws.counters = counters;
+    return enqueue_search(ix, b, n, ws, n, so, out_ids, out_scores, s, false);
+}
+
+const int32_t* batch_diag(const gs_batch_s* b) { return b->diag; }
+
+}  // namespace gs
+
 namespace {
 
 // After a synchronised search: GS_ECAPACITY when the rescored band of some query did not
@@ -1198,7 +1256,9 @@ int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspa
     if (!out_ids || !out_scores) return fail(GS_EINVAL, "null output");
     if (!workspace) return fail(GS_EINVAL, "null workspace");
     DeviceGuard g(ix->device);
-    return enqueue_search(ix, b, b->n_active, workspace, qt, so, out_ids, out_scores, (hipStream_t)hip_stream, true);
+    Workspace ws;
+    carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
+    return enqueue_search(ix, b, b->n_active, ws, qt, so, out_ids, out_scores, (hipStream_t)hip_stream, true);
 }
 
 int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspace_bytes_, int32_t* out_ids,
@@ -1214,8 +1274,10 @@ int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspa
     if (!out_ids || !out_scores || !workspace) return fail(GS_EINVAL, "null workspace or output");
     DeviceGuard g(ix->device);
     hipStream_t s = (hipStream_t)hip_stream;
+    Workspace ws;
+    carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
     // one eager run first: one-time kernel attributes and occupancy queries happen outside the capture
-    rc = enqueue_search(ix, b, b->n_queries, workspace, qt, so, out_ids, out_scores, s, false);
+    rc = enqueue_search(ix, b, b->n_queries, ws, qt, so, out_ids, out_scores, s, false);
     if (rc != GS_OK) return rc;
     GS_HIP(hipStreamSynchronize(s));
     gs_graph gr = new (std::nothrow) gs_graph_s();
@@ -1230,7 +1292,7 @@ int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspa
         delete gr;
         return fail(GS_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
-    rc = enqueue_search(ix, b, b->n_queries, workspace, qt, so, out_ids, out_scores, cs, false);
+    rc = enqueue_search(ix, b, b->n_queries, ws, qt, so, out_ids, out_scores, cs, false);
     e = hipStreamEndCapture(cs, &gr->graph);
     (void)hipStreamDestroy(cs);
     if (rc != GS_OK) {
@@ -1282,11 +1344,13 @@ int32_t gs_autotune(gs_index ix, gs_batch b, void* workspace, size_t workspace_b
         int32_t qt = 1;
         rc = plan_search(ix, b, workspace_bytes_, &cand[i], &so, &qt);
         if (rc != GS_OK) break;
-        rc = enqueue_search(ix, b, b->n_active, workspace, qt, so, out_ids, out_scores, s, false);  // untimed
+        Workspace ws;
+        carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
+        rc = enqueue_search(ix, b, b->n_active, ws, qt, so, out_ids, out_scores, s, false);  // untimed
         if (rc != GS_OK) break;
         he = hipEventRecord(e0, s);
         for (int r = 0; r < reps && rc == GS_OK && he == hipSuccess; r++)
-            rc = enqueue_search(ix, b, b->n_active, workspace, qt, so, out_ids, out_scores, s, false);
+            rc = enqueue_search(ix, b, b->n_active, ws, qt, so, out_ids, out_scores, s, false);
         if (he == hipSuccess) he = hipEventRecord(e1, s);
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.0f;
@@ -1306,6 +1370,18 @@ int32_t gs_autotune(gs_index ix, gs_batch b, void* workspace, size_t workspace_b
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != GS_OK) return rc;
+    // the outputs are the best option set's result: run it once more, last
+    {
+        ScoreOpts so;
+        int32_t qt = 1;
+        rc = plan_search(ix, b, workspace_bytes_, &cand[(size_t)best_i], &so, &qt);
+        if (rc != GS_OK) return rc;
+        Workspace ws;
+        carve_workspace(workspace, ix->n_docs, qt, ix->precision, &ws);
+        rc = enqueue_search(ix, b, b->n_active, ws, qt, so, out_ids, out_scores, s, false);
+        if (rc != GS_OK) return rc;
+        GS_HIP(hipStreamSynchronize(s));
+    }
     if (n_candidates) *n_candidates = (int32_t)cand.size();
     *best = cand[(size_t)best_i];
     return GS_OK;

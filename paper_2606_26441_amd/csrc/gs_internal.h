@@ -8,6 +8,8 @@
 #include <string>
 
 struct gs_batch_s;
+struct gs_index_s;
+struct gs_search_opts;
 
 namespace gs {
 
@@ -52,7 +54,7 @@ struct DevIndex {
     int32_t precision;
     const int64_t* term_off;   // [V+1] start of each padded list
     const int32_t* term_len;   // [V]   real postings per term
-    const int32_t* post_doc;   // [padded_nnz], -1 in padding
+    const int32_t* post_doc;   // [padded_nnz], -1 in padding (GS_KEEP_DOC_IDS only, else null)
     // [padded_nnz] doc id modulo 65536. A doc tile of at most 32768 docs, aligned to its
     // size, lies inside one 65536-aligned range, so the doc-tiled kernels read 2 bytes per
     // posting for the id and recover the offset in the tile from the tile's base.
@@ -62,6 +64,7 @@ struct DevIndex {
     // these lists in whole blocks, 1 byte per posting for the id instead of 2.
     const uint8_t* post_b8;    // [padded_nnz] (0 outside dense lists)
     const int32_t* blk_first;  // [padded_nnz / 64] doc of each block's first posting (-1 if empty)
+    const float* blk_max;      // [padded_nnz / 64] largest stored weight of each block (as float)
     const uint8_t* term_dense; // [V] 1 if the term's list has the byte form
     const void* post_w;        // [padded_nnz] float | bf16 bits (uint16) | uint8
     const int32_t* tile_off;   // [V][n_grains+1] posting offset (relative to the list start)
@@ -139,6 +142,9 @@ struct Workspace {
 
 size_t workspace_bytes(int64_t n_docs, int32_t qt, int32_t precision);
 void carve_workspace(void* base, int64_t n_docs, int32_t qt, int32_t precision, Workspace* ws);
+// A workspace of `rows` query rows in which a search may use any run [r0, r0 + n) (server arena).
+size_t arena_bytes(int64_t n_docs, int64_t rows, int32_t precision);
+void carve_rows(void* base, int64_t n_docs, int64_t rows, int32_t precision, int64_t r0, Workspace* ws);
 
 struct ScoreOpts {
     int kernel;
@@ -169,6 +175,14 @@ __host__ __device__ inline int64_t phase_tile(int phase, int stride, int64_t v) 
 int32_t batch_update(struct ::gs_batch_s* b, const int64_t* q_row_ptr, int32_t n_queries,
                      const int32_t* q_term_ids, const float* q_weights, int64_t q_nnz, const int32_t* k,
                      void* hip_stream, bool wait);
+
+// Search the queries of the batch's last update on rows [r0, r0 + n) of an arena of `rows`
+// rows, with the caller's step counters (16 words, device); asynchronous on s. (Server steps.)
+int32_t search_rows(struct ::gs_index_s* ix, struct ::gs_batch_s* b, void* arena, int64_t rows, int64_t r0,
+                    uint32_t* counters, const struct gs_search_opts* opts, int32_t* out_ids, void* out_scores,
+                    hipStream_t s);
+// Device array of the batch's per-query diagnostics (kDiagWords words per query).
+const int32_t* batch_diag(const struct ::gs_batch_s* b);
 
 // ---- launchers (gs_score.hip) ----
 hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s);

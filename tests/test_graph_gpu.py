@@ -123,3 +123,34 @@ def test_graph_replay_after_a_refill_with_tiny_products(data):
         assert np.array_equal(ids.cpu().numpy(), direct[name][0]), name
         assert np.array_equal(sc.cpu().numpy(), direct[name][1]), name
     graph.close()
+
+
+def test_batch_freed_after_its_index(data):
+    # a batch keeps its own device memory: freeing it after its index must not touch the index
+    gs, torch = _gs()
+    docs, q1, _ = data
+    idx = gs.Index.from_rows(docs, "u8")
+    b = idx.batch(q1, 10)
+    ids, sc = idx.search(b, idx.workspace(q1.n_rows))
+    torch.cuda.synchronize()
+    idx.close()
+    b.close()
+    idx2 = gs.Index.from_rows(docs, "u8")
+    b2 = idx2.batch(q1, 10)
+    ids2, sc2 = idx2.search(b2, idx2.workspace(q1.n_rows))
+    torch.cuda.synchronize()
+    assert np.array_equal(ids.cpu().numpy(), ids2.cpu().numpy())
+    check_batch("u8", docs, q1, ids2.cpu().numpy(), sc2.cpu().numpy(), 10, what="after free")
+    b2.close()
+    idx2.close()
+
+
+def test_atomic_kernel_needs_the_doc_ids(data):
+    gs, torch = _gs()
+    docs, q1, _ = data
+    idx = gs.Index.from_rows(docs, "fp32")
+    with pytest.raises(gs.GsError) as e:
+        idx.search(idx.batch(q1, 10), idx.workspace(4), gs.make_opts("atomic"))
+    assert e.value.code == gs.GS_EUNSUPPORTED
+    full = gs.Index.from_rows(docs, "fp32", keep_doc_ids=True)
+    assert full.info().device_bytes - idx.info().device_bytes == 4 * full.info().padded_nnz

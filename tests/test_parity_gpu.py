@@ -30,7 +30,8 @@ def _gs():
 
 
 def _run(gs, docs, queries, k, precision, kernel="tiled", tile_docs=0, chunk=0, query_tile=0, k_max=None):
-    idx = gs.Index.from_rows(docs, precision, keep_forward=(kernel == "docpar"))
+    idx = gs.Index.from_rows(docs, precision, keep_forward=(kernel == "docpar"),
+                              keep_doc_ids=(kernel == "atomic"))
     b = idx.batch(queries, k, k_max)
     opts = gs.make_opts(kernel, query_tile=query_tile, tile_docs=tile_docs, chunk=chunk)
     ws = idx.workspace(max(1, min(queries.n_rows, 64)), opts)

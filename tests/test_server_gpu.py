@@ -77,17 +77,70 @@ def test_results_alone_equal_results_in_the_mix(data, precision, kernel):
     srv.close()
 
 
-def test_memory_budget_bounds_the_slots(data):
+def test_memory_budget_bounds_the_queries_in_flight(data):
+    # admission by memory: the arena holds as many query rows (score array + selection scratch)
+    # as the budget allows, whatever n_slots x max_batch would take
     gs, _ = _gs()
     docs, qs, k = data
     idx = gs.Index.from_rows(docs, "u8")
-    one = idx.workspace_bytes(8)
-    srv = gs.Server(idx, max_batch=8, n_slots=6, k_max=100, memory_budget=2 * one + one // 2)
-    assert srv.stats()["n_slots"] == 2
+    budget = idx.workspace_bytes(10) + idx.workspace_bytes(1) // 2
+    srv = gs.Server(idx, max_batch=8, n_slots=4, k_max=1000, memory_budget=budget)
+    st = srv.stats()
+    assert st["arena_rows"] == 10 and st["arena_bytes"] <= budget
+    tickets = []
+    for q in range(96):
+        t, w = qs.row(q)
+        tickets.append(srv.submit(t, w, int(k[q])))
+    got = [srv.wait(tickets[q], int(k[q])) for q in range(96)]
+    st = srv.stats()
+    assert 1 <= st["max_in_flight"] <= 10 and st["completed"] == 96
+    rid, rsc = oracle.topk_i64(docs, qs.subset(np.arange(16)), k[:16], k_max=1000)
+    for q in range(16):
+        kq = int(k[q])
+        check_exact_int(got[q][0], got[q][1], rid[q][:kq], rsc[q][:kq], what="budgeted q%d" % q)
     srv.close()
     with pytest.raises(gs.GsError) as e:
-        gs.Server(idx, max_batch=8, n_slots=2, k_max=100, memory_budget=one // 2)
+        gs.Server(idx, max_batch=8, n_slots=2, k_max=100, memory_budget=idx.workspace_bytes(1) // 2)
     assert e.value.code == gs.GS_ECAPACITY
+
+
+def test_poll_and_single_collection(data):
+    gs, _ = _gs()
+    docs, qs, k = data
+    idx = gs.Index.from_rows(docs, "u8")
+    srv = gs.Server(idx, max_batch=4, n_slots=2, k_max=100)
+    t, w = qs.row(0)
+    tk = srv.submit(t, w, 100)
+    res = None
+    for _ in range(200000):
+        res = srv.poll(tk, 100)
+        if res is not None:
+            break
+    assert res is not None
+    ref = srv.wait(srv.submit(t, w, 100), 100)
+    assert np.array_equal(res[0], ref[0]) and np.array_equal(res[1], ref[1])
+    with pytest.raises(gs.GsError) as e:  # a ticket is collected once
+        srv.wait(tk, 100)
+    assert e.value.code == gs.GS_EINVAL
+    with pytest.raises(gs.GsError) as e:
+        srv.poll(tk, 100)
+    assert e.value.code == gs.GS_EINVAL
+    srv.close()
+
+
+def test_bf16_band_overflow_fails_the_request_not_the_server():
+    gs, _ = _gs()
+    from helpers import csr
+    docs = csr([[(0, 1.0)] for _ in range(60_000)] + [[(1, 2.0)]], 4)
+    idx = gs.Index.from_rows(docs, "bf16")
+    srv = gs.Server(idx, max_batch=4, n_slots=1, k_max=100)
+    with pytest.raises(gs.GsError) as e:
+        srv.wait(srv.submit([0], [1.0], 100), 100)
+    assert e.value.code == gs.GS_ECAPACITY
+    ids, sc, _ = srv.wait(srv.submit([1], [1.0], 3), 3)  # the server goes on serving
+    assert ids.tolist() == [60_000, 0, 1] and sc.tolist() == [2.0, 0.0, 0.0]
+    assert srv.stats()["failed"] == 1
+    srv.close()
 
 
 def test_bad_requests_are_rejected(data):

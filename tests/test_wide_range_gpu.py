@@ -82,7 +82,8 @@ def test_wide_range_weights_meet_the_rules(data, precision, kernel, fused):
     docs, (qs, ks, wide) = data
     if kernel in ("atomic", "docpar") and not fused:
         pytest.skip("fused filtering applies to the doc-tiled kernels only")
-    idx = gs.Index.from_rows(docs, precision, keep_forward=(kernel == "docpar"))
+    idx = gs.Index.from_rows(docs, precision, keep_forward=(kernel == "docpar"),
+                              keep_doc_ids=(kernel == "atomic"))
     b = idx.batch(qs, ks, k_max=1024)
     opts = gs.make_opts(kernel, fused_filter=fused)
     ids, sc = idx.search(b, idx.workspace(qs.n_rows, opts), opts)
