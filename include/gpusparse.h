@@ -308,6 +308,22 @@ int32_t gs_search_batch(gs_index index, gs_batch batch, void* workspace, size_t 
                         void* hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): gs_search_batch with
+ * the library's fixed scratch array as the workspace. It calls no hipMalloc,
+ * hipFree or other allocating routine. The array is 128 MiB per GPU, held from
+ * the first call on that GPU until the process ends; queries are processed in
+ * tiles of as many as fit in it (at 8.8M documents: 3 at a time). Every call on
+ * one GPU shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and give undefined results. Calls on one stream
+ * are ordered and safe. Arguments, outputs and asynchrony as gs_search_batch.
+ * Errors: GS_ECAPACITY (a one-query workspace of this index exceeds 128 MiB:
+ * collections above about 33M documents), GS_EINVAL, GS_EUNSUPPORTED, GS_EHIP.
+ */
+int32_t gs_search_batch_noalloc(gs_index index, gs_batch batch, int32_t* out_ids, void* out_scores,
+                                const gs_search_opts* opts, void* hip_stream);
+
+/*
  * Convenience form (the search of Sec. 4.2 from a host CSR of queries):
  * gs_batch_create + gs_search_batch + gs_batch_free.
  * Synchronous (the stream is synchronised before returning). Returns

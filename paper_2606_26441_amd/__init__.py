@@ -122,6 +122,8 @@ def _load() -> ctypes.CDLL:
     lib.gs_workspace_size.restype = i32
     lib.gs_search_batch.argtypes = [vp, vp, vp, sz, vp, vp, P(SearchOpts), vp]
     lib.gs_search_batch.restype = i32
+    lib.gs_search_batch_noalloc.argtypes = [vp, vp, vp, vp, P(SearchOpts), vp]
+    lib.gs_search_batch_noalloc.restype = i32
     lib.gs_search.argtypes = [vp, vp, i32, vp, vp, i64, vp, i32, vp, sz, vp, vp, P(SearchOpts), vp]
     lib.gs_search.restype = i32
     lib.gs_batch_diagnostics.argtypes = [vp, vp]
@@ -271,6 +273,14 @@ class Index:
         if own_ws and stream is not None:
             # the implicit workspace is freed on return while the search may still run on `stream`
             workspace.record_stream(stream)
+        return ids, scores
+
+    def search_noalloc(self, batch: "Batch", out, opts: Optional[SearchOpts] = None, stream=None):
+        """gs_search_batch_noalloc: the search with the library's fixed scratch array (no allocation)."""
+        ids, scores = out
+        _check(lib.gs_search_batch_noalloc(self._h, batch.handle, ids.data_ptr(), scores.data_ptr(),
+                                           ctypes.byref(opts) if opts else None, _stream_ptr(stream)),
+               "gs_search_batch_noalloc")
         return ids, scores
 
     def search_host(self, queries, k, k_max: Optional[int] = None, workspace: Optional[torch.Tensor] = None,

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(HERE, "libgpusparse.so")
 
-SOURCES = ["gs_host.cpp", "gs_server.cpp", "gs_score.hip", "gs_topk.hip", "gs_yardstick.hip"]
+SOURCES = ["gs_host.cpp", "gs_server.cpp", "gs_score.hip", "gs_topk.hip", "gs_yardstick.hip", "gs_noalloc.hip"]
 HEADERS = [os.path.join(CSRC, "gs_internal.h"), os.path.join(ROOT, "include", "gpusparse.h")]
 
 ARCH = "gfx950"

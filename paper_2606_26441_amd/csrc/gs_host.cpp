@@ -1261,6 +1261,31 @@ int32_t gs_search_batch(gs_index ix, gs_batch b, void* workspace, size_t workspa
     return enqueue_search(ix, b, b->n_active, ws, qt, so, out_ids, out_scores, (hipStream_t)hip_stream, true);
 }
 
+int32_t gs_search_batch_noalloc(gs_index ix, gs_batch b, int32_t* out_ids, void* out_scores,
+                                const gs_search_opts* opts, void* hip_stream) {
+    g_err.clear();
+    if (!ix || !b) return fail(GS_EINVAL, "null index or batch");
+    const size_t one = workspace_bytes(ix->n_docs, 1, ix->precision);
+    if (one > kScratchBytes)
+        return fail(GS_ECAPACITY, "a one-query workspace of this index (" + std::to_string(one) +
+                                      " bytes) exceeds the fixed scratch array (" + std::to_string(kScratchBytes) +
+                                      " bytes)");
+    DeviceGuard g(ix->device);
+    void* scratch = nullptr;
+    const hipError_t e = scratch_address(ix->device, &scratch);
+    if (e != hipSuccess) return fail(GS_EHIP, std::string("scratch array address: ") + hipGetErrorString(e));
+    ScoreOpts so;
+    int32_t qt = 1;
+    int32_t rc = plan_search(ix, b, kScratchBytes, opts, &so, &qt);
+    if (rc != GS_OK) return rc;
+    if (b->n_queries == 0 || b->k_max == 0) return GS_OK;
+    if (!out_ids || !out_scores) return fail(GS_EINVAL, "null output");
+    // no timing events: nothing is created or allocated on this path
+    Workspace ws;
+    carve_workspace(scratch, ix->n_docs, qt, ix->precision, &ws);
+    return enqueue_search(ix, b, b->n_active, ws, qt, so, out_ids, out_scores, (hipStream_t)hip_stream, false);
+}
+
 int32_t gs_graph_create(gs_index ix, gs_batch b, void* workspace, size_t workspace_bytes_, int32_t* out_ids,
                         void* out_scores, const gs_search_opts* opts, void* hip_stream, gs_graph* out) {
     g_err.clear();

@@ -29,6 +29,9 @@ constexpr int kFusedCap = 24576;      // of which appended while scoring (fused 
 constexpr int kRefinePasses = 6;      // enough to resolve any 64-bit composite key
 constexpr int kFirstShiftFloat = 52;  // first digit of a float key: bits 30..20
 constexpr int kDiagWords = 8;         // per-query words of gs_batch_diagnostics
+// Fixed scratch array of the allocation-free search (gs_search_batch_noalloc): one per
+// device, 128 MiB (a one-query workspace for collections up to about 33M documents).
+constexpr size_t kScratchBytes = (size_t)128 << 20;
 
 enum Precision { kFP32 = 0, kBF16 = 1, kU8 = 2 };
 
@@ -197,6 +200,11 @@ hipError_t launch_score_docpar(const DevIndex& ix, const DevBatch& qb, int32_t q
                                const ScoreOpts& o, const Workspace& ws, hipStream_t s);
 hipError_t launch_hist1(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                         const Workspace& ws, hipStream_t s);
+// ---- gs_noalloc.hip ----
+// Device address of `device`'s copy of the fixed scratch array (kScratchBytes), looked up
+// once per device with that device current (the caller makes it current).
+hipError_t scratch_address(int device, void** out);
+
 // ---- launchers (gs_yardstick.hip) ----
 hipError_t launch_copy16(void* dst, const void* src, int64_t n16, hipStream_t s);
 // LDS atomic-add throughput: op 0 uint32, 1 uint64, 2 float, 3 double; pattern 0 scattered, 1 consecutive
