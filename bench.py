@@ -59,8 +59,12 @@ def parse():
     ap.add_argument("--batched", default="u8,bf16",
                     help="precisions for the 4,096-query uneven batch (autotuned, graph vs plain), or 'none'")
     ap.add_argument("--batched-queries", type=int, default=4096)
-    ap.add_argument("--serving", default="200,800,2000,12000,16000", help="Poisson arrival rates (QPS) for the serving loop, or 'none'")
-    ap.add_argument("--serving-seconds", type=float, default=8.0)
+    ap.add_argument("--top10", type=int, default=1, help="also time every form at top-10 (1) or not (0)")
+    ap.add_argument("--serving", default="200,800,2000,16000", help="Poisson arrival rates (QPS) for the serving loop, or 'none'")
+    ap.add_argument("--serving-seconds", type=float, default=30.0, help="duration of each rate up to 2000 QPS")
+    ap.add_argument("--serving-seconds-high", type=float, default=10.0, help="duration of each rate above 2000 QPS")
+    ap.add_argument("--serving-budget-gib", type=float, default=8.0,
+                    help="device memory for the in-flight queries' score buffers (admission by memory)")
     ap.add_argument("--serving-precision", default="u8")
     ap.add_argument("--serving-batch", type=int, default=64, help="most queries per device step of the server")
     ap.add_argument("--serving-slots", type=int, default=4, help="device slots (concurrent steps) of the server")
@@ -87,6 +91,12 @@ def algorithmic_bytes(df, queries, n_docs, wbytes, idbytes, written_docs=None):
 
 
 _C_TOKEN = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'', re.S)
+
+
+def survey_model_bytes(p_q, n_docs, wbytes):
+    """The per-query byte model of the scope table: P_q * (4 + s_w) + 8 N (postings with a 4-byte doc id and
+    an s_w-byte weight, one write and one read of the 4-byte score array), summed over the queries."""
+    return int(np.sum(p_q.astype(np.float64) * (4 + wbytes)) + p_q.shape[0] * 8 * n_docs)
 
 
 def code_digest(files):
@@ -191,8 +201,26 @@ def lds_atomic_rates(gs, torch, workgroups=2048, iters=1024, reps=5):
     return out
 
 
-def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_forward=False, host_steps=0):
-    idx = gs.Index.from_rows(docs, precision, keep_forward=keep_forward)
+class IndexCache:
+    """One resident index per (precision, forward rows kept, 32-bit doc ids kept), built on first use:
+    the document-parallel kernel needs the forward rows, the global-atomic kernel the doc ids."""
+
+    def __init__(self, gs, docs):
+        self.gs, self.docs, self.idx = gs, docs, {}
+
+    def get(self, precision, kernel="tiled"):
+        key = (precision, kernel == "docpar" or precision == "bf16", kernel == "atomic")
+        if key not in self.idx:
+            log("index %s%s%s ..." % (precision, " + forward rows" if key[1] else "", " + doc ids" if key[2] else ""))
+            self.idx[key] = self.gs.Index.from_rows(self.docs, precision, keep_forward=key[1], keep_doc_ids=key[2])
+        return self.idx[key]
+
+    def drop(self, precision):
+        for key in [k for k in self.idx if k[0] == precision]:
+            self.idx.pop(key).close()
+
+
+def time_form(gs, torch, idx, queries, k, opts, steps, warmup, host_steps=0):
     batch = idx.batch(queries, k)
     nq = queries.n_rows
     ws = idx.workspace(nq, opts)
@@ -229,12 +257,11 @@ def time_form(gs, torch, docs, queries, k, precision, opts, steps, warmup, keep_
         res["host_ms"] = np.array(host_ms)
     del ws, ids, sc
     batch.close()
-    idx.close()
     torch.cuda.empty_cache()
     return res
 
 
-def run_batched(gs, torch, docs, args):
+def run_batched(gs, torch, docs, args, indexes):
     """Uneven batch: lognormal query lengths (median 25, 5..250), k mixed over {10, 100, 1000}; autotuned
     options; one persistent-or-grid launch per step; hipGraph replay vs plain launches; oracle-checked sample."""
     import workload
@@ -248,10 +275,10 @@ def run_batched(gs, torch, docs, args):
     k = workload.k_mix(nq, seed=4)
     res = {"workload": w.name, "queries": nq, "query_nnz_mean": round(queries.nnz / nq, 2),
            "query_nnz_max": int(np.diff(queries.row_ptr).max()), "k_mix": [10, 100, 1000]}
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    threads = host_threads()["threads"]
     for prec in [p for p in args.batched.split(",") if p]:
-        log("batched %s: index + autotune ..." % prec)
-        idx = gs.Index.from_rows(docs, prec)
+        idx = indexes.get(prec)
+        log("batched %s: autotune ..." % prec)
         tune_q = queries.subset(np.arange(min(512, nq)))
         tb = idx.batch(tune_q, k[: tune_q.n_rows], k_max=1000)
         best, table = idx.autotune(tb, reps=1)
@@ -337,43 +364,57 @@ def run_batched(gs, torch, docs, args):
                                                                          status))
         sb.close()
         batch.close()
-        idx.close()
         del g16, sws, sids, ssc
         torch.cuda.empty_cache()
     return res
 
 
-def run_serving(gs, torch, docs, args):
-    """Poisson arrivals into the continuous-batching loop; latency = submission to results on the host."""
+def run_serving(gs, torch, docs, args, indexes):
+    """Poisson arrivals into the continuous-batching loop; latency = submission to results on the host.
+
+    Admission is by memory: the server's workspace arena holds as many query rows (score array plus
+    selection scratch) as the budget allows. The first requests of the first rate are checked
+    against the oracle."""
     import threading
+    import oracle
     import workload
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity_rules import check_exact_f64, check_exact_int
 
     prec = args.serving_precision
-    idx = gs.Index.from_rows(docs, prec)
+    idx = indexes.get(prec)
     pool = workload.queries_lognormal(8192, seed=91)
     ks = workload.k_mix(8192, seed=92)
     max_batch, n_slots = args.serving_batch, args.serving_slots
-    srv = gs.Server(idx, max_batch=max_batch, n_slots=n_slots, k_max=1000, opts=gs.make_opts(args.serving_kernel))
+    budget = int(args.serving_budget_gib * (1 << 30))
+    srv = gs.Server(idx, max_batch=max_batch, n_slots=n_slots, k_max=1000, memory_budget=budget,
+                    opts=gs.make_opts(args.serving_kernel))
+    st = srv.stats()
     res = {"precision": prec, "kernel": args.serving_kernel, "max_batch": max_batch, "n_slots": n_slots,
-           "slot_bytes": srv.stats()["slot_bytes"],
+           "memory_budget": budget, "arena_rows": st["arena_rows"], "row_bytes": st["row_bytes"],
            "query_law": "lognormal median 25, sigma 0.8, [5, 250]; k over {10, 100, 1000}"}
     for q in range(64):  # warm-up
         t, w = pool.row(q)
         srv.wait(srv.submit(t, w, int(ks[q])), int(ks[q]))
-    for rate in [float(r) for r in args.serving.split(",") if r]:
-        arrivals = workload.poisson_arrivals(rate, args.serving_seconds, seed=int(rate))
+    sample = {}
+    for ri, rate in enumerate([float(r) for r in args.serving.split(",") if r]):
+        secs = args.serving_seconds if rate <= 2000 else args.serving_seconds_high
+        arrivals = workload.poisson_arrivals(rate, secs, seed=int(rate))
         n = arrivals.shape[0]
         tickets = [None] * n
         lat = np.zeros(n)
         done_at = np.zeros(n)
+        keep = 8 if ri == 0 else 0
 
         def collector():
             for i in range(n):
                 while tickets[i] is None:
                     time.sleep(1e-5)
                 kq = int(ks[i % 8192])
-                _, _, lat[i] = srv.wait(tickets[i], kq)
+                ids_i, sc_i, lat[i] = srv.wait(tickets[i], kq)
                 done_at[i] = time.perf_counter()
+                if i < keep:
+                    sample[i] = (ids_i.copy(), sc_i.copy())
 
         before = srv.stats()
         th = threading.Thread(target=collector)
@@ -386,21 +427,57 @@ def run_serving(gs, torch, docs, args):
             t, w = pool.row(i % 8192)
             tickets[i] = srv.submit(t, w, int(ks[i % 8192]))
         th.join()
-        span = max(done_at.max() - t0, args.serving_seconds)
+        span = max(done_at.max() - t0, secs)
         after = srv.stats()
         steps = after["device_steps"] - before["device_steps"]
         res["rate_%d" % int(rate)] = {
-            "offered_qps": rate, "requests": n, "sustained_qps": round(n / span, 1),
+            "offered_qps": rate, "seconds": secs, "requests": n, "sustained_qps": round(n / span, 1),
             "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_batch": round((after["completed"] - before["completed"]) / max(steps, 1), 2),
-            "max_in_flight": after["max_in_flight"]}
-        log("serving %s @%d QPS: sustained %.1f, p50 %.2f ms, p99 %.2f ms, mean batch %.1f"
-            % (prec, rate, n / span, np.percentile(lat, 50), np.percentile(lat, 99),
+            "max_in_flight": after["max_in_flight"], "failed": after["failed"] - before["failed"]}
+        log("serving %s @%d QPS for %.0f s: sustained %.1f, p50 %.2f ms, p99 %.2f ms, mean batch %.1f"
+            % (prec, rate, secs, n / span, np.percentile(lat, 50), np.percentile(lat, 99),
                res["rate_%d" % int(rate)]["mean_batch"]))
     srv.close()
-    idx.close()
+    # oracle check of the first served requests (same queries, same k)
+    if sample:
+        s = len(sample)
+        sub = pool.subset(np.arange(s))
+        kk = ks[:s]
+        threads = host_threads()["threads"]
+        try:
+            if prec == "u8":
+                rid, rsc = oracle.topk_i64(docs, sub, kk, k_max=1000, n_threads=threads)
+                for i in range(s):
+                    check_exact_int(sample[i][0], sample[i][1], rid[i][:kk[i]], rsc[i][:kk[i]], what="served")
+                res["parity"] = "bit-exact on the first %d served requests" % s
+            elif prec == "bf16":
+                rid, rsc = oracle.topk_f64(docs, sub, kk, k_max=1000, n_threads=threads)
+                for i in range(s):
+                    check_exact_f64(sample[i][0], sample[i][1], rid[i][:kk[i]], rsc[i][:kk[i]], what="served")
+                res["parity"] = "ids and fp64 scores identical on the first %d served requests" % s
+        except AssertionError as e:
+            res["parity"] = "MISMATCH: " + str(e)[:160]
+        log("serving parity: %s" % res.get("parity"))
     torch.cuda.empty_cache()
     return res
+
+
+def host_threads():
+    """Host CPUs for the oracle: the process's affinity set, capped by OMP_NUM_THREADS when it is set
+    (a shared GPU machine gives each GPU a CPU share and sets it)."""
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"threads": min(aff, omp) if omp > 0 else aff, "affinity_cpus": aff, "nproc": os.cpu_count(),
+            "omp_num_threads": omp or None, "cpu_model": model}
 
 
 def main():
@@ -426,6 +503,7 @@ def main():
     log("collection: %d postings; queries: %d (mean nnz %.1f)" % (docs.nnz, nq, queries.nnz / max(nq, 1)))
     df = np.bincount(docs.terms, minlength=docs.vocab)
     opts = gs.make_opts(args.kernel, tile_docs=args.tile_docs, chunk=args.chunk, fused_filter=not args.no_fused)
+    indexes = IndexCache(gs, docs)
 
     # yardstick: a plain 2 GiB device copy (reads and writes exactly its size once)
     src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
@@ -442,12 +520,14 @@ def main():
     del src, dst
     torch.cuda.empty_cache()
     log("device copy yardstick: %.0f GB/s (read + write)" % copy_gbs)
-    lds_rates = lds_atomic_rates(gs, torch)
-    log("LDS atomic yardstick: %s" % lds_rates)
+    lds_rates = None if args.profile else lds_atomic_rates(gs, torch)
+    if lds_rates:
+        log("LDS atomic yardstick: %s" % lds_rates)
 
     log("main form: %s / %s, %d warmup + %d timed steps" % (args.precision, args.kernel, args.warmup, args.steps))
-    main_res = time_form(gs, torch, docs, queries, args.k, args.precision, opts, args.steps, args.warmup,
-                         keep_forward=(args.kernel == "docpar"), host_steps=0 if args.profile else 3)
+    main_idx = indexes.get(args.precision, args.kernel)
+    main_res = time_form(gs, torch, main_idx, queries, args.k, opts, args.steps, args.warmup,
+                         host_steps=0 if args.profile else 3)
     written = None
     tile_docs = args.tile_docs or (8192 if args.precision == "fp32" else 16384)
     n_tiles = (n_docs + tile_docs - 1) // tile_docs
@@ -459,20 +539,23 @@ def main():
         idbytes = np.where(main_res["dense_terms"] != 0, 1.0 + 4.0 / 64.0, 2.0)
     else:
         idbytes = 2 if args.kernel in ("tiled", "shared") else 4
-    p_q, score_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision], idbytes,
-                                                     written)
+    p_q, layout_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision], idbytes,
+                                                      written)
+    survey_bytes = survey_model_bytes(p_q, n_docs, WEIGHT_BYTES[args.precision])
     if args.kernel == "docpar":
         # document-parallel: every forward row (term id + fp32 weight) per query, plus one score write
-        score_bytes = nq * (docs.nnz * 8 + n_docs * 4)
-        step_bytes = score_bytes + nq * n_docs * 4
+        layout_bytes = nq * (docs.nnz * 8 + n_docs * 4)
+        survey_bytes = nq * (docs.nnz * 8 + n_docs * 4)
+        step_bytes = layout_bytes + nq * n_docs * 4
     ms_per_step = main_res["total_ms"] / args.steps
     qps = nq * args.steps / (main_res["total_ms"] / 1e3)
     t = main_res["timing"]
     score_ms = t["score_ms"] / max(t["score_launches"], 1)
     select_ms = t["select_ms"] / max(t["select_launches"], 1)
-    achieved = score_bytes / (score_ms / 1e3) / 1e9
-    log("QPS %.1f  ms/step %.2f  score %.2f ms  select %.2f ms  score kernel %.0f GB/s"
-        % (qps, ms_per_step, score_ms, select_ms, achieved))
+    achieved = survey_bytes / (score_ms / 1e3) / 1e9
+    layout_gbs = layout_bytes / (score_ms / 1e3) / 1e9
+    log("QPS %.1f  ms/step %.2f  score %.2f ms  select %.2f ms  scoring: %.0f GB/s effective (model bytes), "
+        "%.0f GB/s on its layout bytes" % (qps, ms_per_step, score_ms, select_ms, achieved, layout_gbs))
 
     kernel_name = {"tiled": "k_score_tiled", "shared": "k_score_persistent", "atomic": "k_score_atomic",
                    "docpar": "k_score_docpar"}[args.kernel]
@@ -497,16 +580,24 @@ def main():
                    "precision": args.precision, "kernel": args.kernel, "tile_docs": tile_docs,
                    "chunk": args.chunk or 1024, "query_nnz_mean": round(queries.nnz / max(nq, 1), 2),
                    "postings_per_query_mean": int(p_q.mean())},
-        "roofline": {"bound": "hbm", "kernel": kernel_name,
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_source": traffic_src,
-                     "algorithmic_bytes_per_launch": score_bytes, "launch_ms": round(score_ms, 4),
-                     "queries_per_launch": nq},
+        "roofline": {
+            "bound": "hbm", "kernel": kernel_name,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "frac_kind": "effective: the per-query model bytes P_q*(4+s_w) + 8N (postings with 4 B doc ids, one "
+                         "score write and read) over the scoring launches' time; above 1 when the kernel moves "
+                         "fewer bytes than the model (2- or 1-byte doc ids, score rows of seed tiles only)",
+            "algorithmic_bytes_per_launch": survey_bytes,
+            "layout_bytes_per_launch": layout_bytes,
+            "layout_frac": round(layout_gbs / HBM_PEAK_GBS, 4),
+            "hbm_frac_counters": None if traffic is None else round(traffic / (score_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                                                    4),
+            "traffic_source": traffic_src,
+            "launch_ms": round(score_ms, 4), "queries_per_launch": nq},
         "step": {"p50_ms": round(float(np.percentile(main_res["step_ms"], 50)), 3),
                  "p99_ms": round(float(np.percentile(main_res["step_ms"], 99)), 3),
                  "score_ms": round(score_ms, 3), "select_ms": round(select_ms, 3),
-                 "hbm_frac_whole_step": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+                 "hbm_frac_whole_step_layout": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "memory": {"index_bytes": main_res["device_bytes"], "workspace_bytes": main_res["ws_bytes"]},
         "hbm_copy_GBs": round(copy_gbs, 1),
         "lds_atomic": lds_rates,
@@ -517,30 +608,45 @@ def main():
                     % len(main_res["host_ms"])},
         "selection": {"candidates_mean": float(main_res["diag"][:, 0].mean()),
                       "refine_passes_max": int(main_res["diag"][:, 1].max()),
-                      "overflow": int(main_res["diag"][:, 3].max())},
+                      "overflow": int(main_res["diag"][:, 3].max()),
+                      "wide_range_queries": int((main_res["diag"][:, 4] == 2).sum())},
     }
 
-    forms = {}
+    main_name = args.precision if args.kernel == "tiled" else args.precision + ":" + args.kernel
+    specs = []
     if not args.profile and args.forms != "none":
         for spec in [f for f in args.forms.split(",") if f]:
             prec, _, kern = spec.partition(":")
             kern = kern or "tiled"
-            if (prec, kern) == (args.precision, args.kernel):
-                continue
+            if (prec, kern) != (args.precision, args.kernel):
+                specs.append((prec, kern))
+    forms = {}
+    for prec, kern in specs:
+        name = prec if kern == "tiled" else prec + ":" + kern
+        log("form %s ..." % name)
+        fsteps = max(3, args.steps // 2)
+        r = time_form(gs, torch, indexes.get(prec, kern), queries, args.k,
+                      gs.make_opts(kern), fsteps, 1)
+        ms = r["total_ms"] / fsteps
+        t = r["timing"]
+        forms[name] = {"qps": round(nq / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
+                       "score_ms": round(t["score_ms"] / max(t["score_launches"], 1), 3),
+                       "select_ms": round(t["select_ms"] / max(t["select_launches"], 1), 3),
+                       "index_bytes": r["device_bytes"],
+                       "overflow": int(r["diag"][:, 3].max())}
+        forms[name]["_res"] = r
+        log("form %s: QPS %.1f" % (name, forms[name]["qps"]))
+
+    # top-10 of the same batch for every form (the paper's Fig. 1 cut-off), oracle-checked below
+    top10 = {}
+    if not args.profile and args.top10 and args.k != 10:
+        for prec, kern in [(args.precision, args.kernel)] + specs:
             name = prec if kern == "tiled" else prec + ":" + kern
-            log("form %s ..." % name)
-            fsteps = max(3, args.steps // 2)
-            r = time_form(gs, torch, docs, queries, args.k, prec, gs.make_opts(kern), fsteps, 1,
-                          keep_forward=(kern == "docpar"))
-            ms = r["total_ms"] / fsteps
-            t = r["timing"]
-            forms[name] = {"qps": round(nq / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
-                           "score_ms": round(t["score_ms"] / max(t["score_launches"], 1), 3),
-                           "select_ms": round(t["select_ms"] / max(t["select_launches"], 1), 3),
-                           "index_bytes": r["device_bytes"],
-                           "overflow": int(r["diag"][:, 3].max())}
-            forms[name]["_res"] = r
-            log("form %s: QPS %.1f" % (name, forms[name]["qps"]))
+            r = time_form(gs, torch, indexes.get(prec, kern), queries, 10,
+                          gs.make_opts(kern), 3, 1)
+            ms = r["total_ms"] / 3
+            top10[name] = {"qps": round(nq / (ms / 1e3), 2), "ms_per_step": round(ms, 3), "_res": r}
+            log("top-10 %s: QPS %.1f" % (name, top10[name]["qps"]))
 
     if not args.profile and args.cpu_sample > 0:
         import oracle
@@ -549,59 +655,77 @@ def main():
 
         s = min(args.cpu_sample, nq)
         sample = queries.subset(np.arange(s))
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
-        log("CPU oracle on %d queries with %d threads ..." % (s, threads))
+        ht = host_threads()
+        threads = ht["threads"]
+        log("CPU oracle on %d queries with %d threads (%s) ..." % (s, threads, ht["cpu_model"]))
         t0 = time.time()
         rid, rsc = oracle.topk_f64(docs, sample, args.k, n_threads=threads)
         cpu_s = time.time() - t0
         out["cpu_baseline"] = {"value": round(s / cpu_s, 4), "unit": "queries/s", "cores": threads,
                                "kind": "oracle",
                                "sample": "first %d of the %d queries, full %d-doc collection, exact fp64 top-%d "
-                                         "with full sort; %.1f s wall" % (s, nq, n_docs, args.k, cpu_s)}
+                                         "with full sort; %.1f s wall" % (s, nq, n_docs, args.k, cpu_s),
+                               "nproc": ht["nproc"], "affinity_cpus": ht["affinity_cpus"],
+                               "omp_num_threads": ht["omp_num_threads"], "cpu_model": ht["cpu_model"]}
         t0 = time.time()
         oracle.topk_f64(docs, queries.subset(np.arange(1)), args.k, n_threads=1)
         out["cpu_single_thread"] = {"ms_per_query": round((time.time() - t0) * 1e3, 1),
                                     "sample": "the oracle on the first query, one thread"}
         log("CPU oracle, one thread: %.0f ms per query" % out["cpu_single_thread"]["ms_per_query"])
-        # full-size parity of the timed launch configuration on the same sample
-        checked = {}
-        rid8 = rsc8 = None
-        s8 = min(4, s)
-        try:
-            for name, res in [(args.precision if args.kernel == "tiled" else args.precision + ":" + args.kernel,
-                               main_res)] + [(n, f["_res"]) for n, f in forms.items()]:
-                prec = name.split(":")[0]
-                if prec == "fp32":
-                    for q in range(s):
-                        t_, w_ = queries.row(q)
-                        check_fp32(docs, t_, w_, res["ids"][q], res["scores"][q], rid[q], rsc[q], args.k, what=name)
-                    checked[name] = "within 1e-5, ids equal up to tolerance swaps (%d queries)" % s
-                elif prec == "bf16":
-                    for q in range(s):
-                        check_exact_f64(res["ids"][q], res["scores"][q], rid[q], rsc[q], what=name)
-                    checked[name] = "ids and fp64 scores identical (%d queries)" % s
-                else:
-                    if rid8 is None:
-                        rid8, rsc8 = oracle.topk_i64(docs, queries.subset(np.arange(s8)), args.k, n_threads=threads)
-                    for q in range(s8):
-                        check_exact_int(res["ids"][q], res["scores"][q], rid8[q], rsc8[q], what=name)
-                    checked[name] = "bit-exact (%d queries)" % s8
-        except AssertionError as e:
-            checked["error"] = str(e)[:200]
-        out["parity_sample"] = checked
-        log("parity: %s" % checked)
+
+        def check(results, k, s_f, rid_f, rsc_f, s8, cache8):
+            checked = {}
+            try:
+                for name, res in results:
+                    prec = name.split(":")[0]
+                    if prec == "fp32":
+                        for q in range(s_f):
+                            t_, w_ = queries.row(q)
+                            check_fp32(docs, t_, w_, res["ids"][q], res["scores"][q], rid_f[q], rsc_f[q], k,
+                                       what=name)
+                        checked[name] = "within 1e-5, ids equal up to tolerance swaps (%d queries)" % s_f
+                    elif prec == "bf16":
+                        for q in range(s_f):
+                            check_exact_f64(res["ids"][q], res["scores"][q], rid_f[q], rsc_f[q], what=name)
+                        checked[name] = "ids and fp64 scores identical (%d queries)" % s_f
+                    else:
+                        if not cache8:
+                            cache8.extend(oracle.topk_i64(docs, queries.subset(np.arange(s8)), k, n_threads=threads))
+                        for q in range(s8):
+                            check_exact_int(res["ids"][q], res["scores"][q], cache8[0][q], cache8[1][q], what=name)
+                        checked[name] = "bit-exact (%d queries)" % s8
+            except AssertionError as e:
+                checked["error"] = str(e)[:200]
+            return checked
+
+        # full-size parity of the timed launch configurations on the same sample
+        out["parity_sample"] = check([(main_name, main_res)] + [(n, f["_res"]) for n, f in forms.items()], args.k,
+                                     s, rid, rsc, min(4, s), [])
+        log("parity: %s" % out["parity_sample"])
+        if top10:
+            s10 = min(4, s)
+            rid10, rsc10 = oracle.topk_f64(docs, queries.subset(np.arange(s10)), 10, n_threads=threads)
+            chk10 = check([(n, f["_res"]) for n, f in top10.items()], 10, s10, rid10, rsc10, s10, [])
+            for n in top10:
+                top10[n]["parity"] = chk10.get(n, chk10.get("error"))
+            log("top-10 parity: %s" % chk10)
         out["score_error"] = score_error(oracle, docs, queries, s, args.k, rid,
                                          [(args.precision, main_res)] + [(n.split(":")[0], f["_res"])
                                                                          for n, f in forms.items()])
         log("score error: %s" % out["score_error"])
-    if not args.profile and args.batched != "none":
-        out["batched"] = run_batched(gs, torch, docs, args)
-    if not args.profile and args.serving != "none":
-        out["serving"] = run_serving(gs, torch, docs, args)
-    for f in forms.values():
+    for f in list(forms.values()) + list(top10.values()):
         f.pop("_res", None)
     if forms:
         out["forms"] = forms
+    if top10:
+        out["top10"] = top10
+    if not args.profile:
+        indexes.drop("fp32")  # the batched and serving legs use the bf16 and uint8 indexes
+        torch.cuda.empty_cache()
+    if not args.profile and args.batched != "none":
+        out["batched"] = run_batched(gs, torch, docs, args, indexes)
+    if not args.profile and args.serving != "none":
+        out["serving"] = run_serving(gs, torch, docs, args, indexes)
     print(json.dumps(out), flush=True)
 
 
