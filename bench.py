@@ -47,11 +47,11 @@ def parse():
     ap.add_argument("--batch", type=int, default=0, help="override the number of queries")
     ap.add_argument("--k", type=int, default=1000)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "u8"])
-    ap.add_argument("--kernel", default="tiled", choices=["tiled", "atomic", "docpar", "shared"])
+    ap.add_argument("--kernel", default="tiled", choices=["tiled", "atomic", "docpar", "shared", "group"])
     ap.add_argument("--tile-docs", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--forms", default="u8,bf16,fp32:shared,u8:shared,bf16:shared",
-                    help="other precision[:kernel] forms to time (comma list, or 'none')")
+                    help="other precision[:kernel[:chunk[:prune]]] forms to time (comma list, or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16, help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--profile", action="store_true", help="main form only, no CPU leg (for profiler runs)")
     ap.add_argument("--lds-probe", action="store_true", help="only the LDS atomic-add yardstick (for profiler runs)")
@@ -531,14 +531,14 @@ def main():
     written = None
     tile_docs = args.tile_docs or (8192 if args.precision == "fp32" else 16384)
     n_tiles = (n_docs + tile_docs - 1) // tile_docs
-    if (not args.no_fused and args.kernel in ("tiled", "shared") and args.precision != "bf16" and nq >= 32
+    if (not args.no_fused and args.kernel in ("tiled", "shared", "group") and args.precision != "bf16" and nq >= 32
             and args.k <= 1024 and n_tiles >= 16):
         # fused candidate filtering: score rows of the seed tiles (every 8th) only
         written = sum(min(tile_docs, n_docs - t * tile_docs) for t in range(0, n_tiles, 8))
     if args.kernel == "tiled" and args.precision != "u8":
         idbytes = np.where(main_res["dense_terms"] != 0, 1.0 + 4.0 / 64.0, 2.0)
     else:
-        idbytes = 2 if args.kernel in ("tiled", "shared") else 4
+        idbytes = 2 if args.kernel in ("tiled", "shared", "group") else 4
     p_q, layout_bytes, step_bytes = algorithmic_bytes(df, queries, n_docs, WEIGHT_BYTES[args.precision], idbytes,
                                                       written)
     survey_bytes = survey_model_bytes(p_q, n_docs, WEIGHT_BYTES[args.precision])
@@ -558,7 +558,7 @@ def main():
         "%.0f GB/s on its layout bytes" % (qps, ms_per_step, score_ms, select_ms, achieved, layout_gbs))
 
     kernel_name = {"tiled": "k_score_tiled", "shared": "k_score_persistent", "atomic": "k_score_atomic",
-                   "docpar": "k_score_docpar"}[args.kernel]
+                   "docpar": "k_score_docpar", "group": "k_score_group"}[args.kernel]
     traffic, traffic_src = (None, None)
     if args.n_docs in (0, w.n_docs) and nq == w.n_queries and args.k == 1000 and not args.no_fused \
             and not args.tile_docs and not args.chunk:
@@ -616,17 +616,21 @@ def main():
     specs = []
     if not args.profile and args.forms != "none":
         for spec in [f for f in args.forms.split(",") if f]:
-            prec, _, kern = spec.partition(":")
-            kern = kern or "tiled"
-            if (prec, kern) != (args.precision, args.kernel):
-                specs.append((prec, kern))
+            parts = spec.split(":")
+            prec, kern = parts[0], (parts[1] if len(parts) > 1 and parts[1] else "tiled")
+            chunk = int(parts[2]) if len(parts) > 2 and parts[2] else 0
+            prune = len(parts) > 3 and parts[3] == "prune"
+            if (prec, kern, chunk, prune) != (args.precision, args.kernel, args.chunk, False):
+                specs.append((prec, kern, chunk, prune))
     forms = {}
-    for prec, kern in specs:
+    for prec, kern, chunk, prune in specs:
         name = prec if kern == "tiled" else prec + ":" + kern
+        name += (":%d" % chunk) if chunk else ""
+        name += ":prune" if prune else ""
         log("form %s ..." % name)
         fsteps = max(3, args.steps // 2)
         r = time_form(gs, torch, indexes.get(prec, kern), queries, args.k,
-                      gs.make_opts(kern), fsteps, 1)
+                      gs.make_opts(kern, chunk=chunk, prune=prune), fsteps, 1)
         ms = r["total_ms"] / fsteps
         t = r["timing"]
         forms[name] = {"qps": round(nq / (ms / 1e3), 2), "ms_per_step": round(ms, 3),
@@ -634,16 +638,20 @@ def main():
                        "select_ms": round(t["select_ms"] / max(t["select_launches"], 1), 3),
                        "index_bytes": r["device_bytes"],
                        "overflow": int(r["diag"][:, 3].max())}
+        if prune:
+            forms[name]["pruned_blocks_per_query"] = round(float(r["diag"][:, 6].mean()), 1)
         forms[name]["_res"] = r
         log("form %s: QPS %.1f" % (name, forms[name]["qps"]))
 
     # top-10 of the same batch for every form (the paper's Fig. 1 cut-off), oracle-checked below
     top10 = {}
     if not args.profile and args.top10 and args.k != 10:
-        for prec, kern in [(args.precision, args.kernel)] + specs:
+        for prec, kern, chunk, prune in [(args.precision, args.kernel, args.chunk, False)] + specs:
             name = prec if kern == "tiled" else prec + ":" + kern
+            name += (":%d" % chunk) if chunk else ""
+            name += ":prune" if prune else ""
             r = time_form(gs, torch, indexes.get(prec, kern), queries, 10,
-                          gs.make_opts(kern), 3, 1)
+                          gs.make_opts(kern, chunk=chunk, prune=prune), 3, 1)
             ms = r["total_ms"] / 3
             top10[name] = {"qps": round(nq / (ms / 1e3), 2), "ms_per_step": round(ms, 3), "_res": r}
             log("top-10 %s: QPS %.1f" % (name, top10[name]["qps"]))

@@ -87,11 +87,18 @@ enum gs_kernel {
                              atomics into the score array (the paper's Sec. 5.2 form) */
     GS_KERNEL_DOCPAR = 3, /* document-parallel: per (query, doc) gather over the
                              forward rows, no atomics (Sec. 5.3); needs GS_KEEP_FORWARD */
-    GS_KERNEL_SHARED = 4  /* batched shared traversal: the TILED work items on a
+    GS_KERNEL_SHARED = 4, /* batched shared traversal: the TILED work items on a
                              persistent grid, taken tile by tile (every query of a
                              doc tile on one XCD, longest queries first), so a
                              tile's posting segments are read from HBM once and
                              from that XCD's L2 for the other queries holding them */
+    GS_KERNEL_GROUP = 5   /* batched shared traversal with explicit sharing: per (doc tile
+                             of 8192, group of 2 queries), the segments of
+                             the union of the group's terms; each posting chunk is loaded
+                             once and added into the LDS tile of every query of the group
+                             holding its term. Tile 8192 and chunks of 256-1024 only
+                             (GS_EUNSUPPORTED otherwise); a search whose workspace holds
+                             fewer than all its queries runs GS_KERNEL_SHARED instead */
 };
 
 #define GS_MAX_K 4096        /* largest k per query */
@@ -111,7 +118,17 @@ typedef struct gs_search_opts {
                                 8th doc tile, then only those tiles' scores are
                                 scanned and, for fp32 and uint8, written); 1 writes
                                 and scans every score row */
-    int32_t reserved[3]; /* must be 0 */
+    int32_t prune;       /* 1: exact block-max pruning in the non-seed tiles (Sec. 5.3 leaves
+                            GPU pruning aside; built here as an option). Needs GS_KERNEL_TILED,
+                            GS_FP32 or GS_U8, the default tile, chunk 1024 (else
+                            GS_EUNSUPPORTED) and fused filtering (a search of 32+ queries,
+                            k <= 2048; otherwise nothing is pruned). Per query, the terms
+                            whose upper bounds (w_q times the term's largest weight) sum below
+                            the seed bound's score are non-essential; after the others are
+                            scored, each 64-posting block of a non-essential term is skipped
+                            unread when no doc it can hold can reach the bound. The results
+                            are the same as without it, bit for bit */
+    int32_t reserved[2]; /* must be 0 */
 } gs_search_opts;
 
 typedef struct gs_index_info_t {
@@ -135,6 +152,12 @@ const char* gs_version(void);
 const char* gs_status_string(int32_t status);
 /* Message of the last failing call on this thread ("" if none). */
 const char* gs_last_error(void);
+
+/* Test hook (fault injection, not for production use): after n more device or pinned
+ * host allocations made by the library, the next one fails as out of memory, once;
+ * n < 0 disarms it. Process-wide. Lets tests check the GS_ENOMEM paths (no leaks,
+ * no partial objects). Always returns GS_OK. */
+int32_t gs_debug_fail_alloc(int64_t n);
 
 /* ------------------------------------------------------------ index build -- */
 
@@ -389,7 +412,8 @@ int32_t gs_autotune(gs_index index, gs_batch batch, void* workspace, size_t work
  *       2 wide range (fixed-point error too large for the k-th score: every
  *       tile summed again in fp64);
  *   [5] 1 if fused candidate filtering produced the candidates;
- *   [6], [7] 0.
+ *   [6] 64-posting blocks skipped by pruning (opts.prune);
+ *   [7] 0.
  */
 int32_t gs_batch_diagnostics(gs_batch batch, int32_t* out);
 

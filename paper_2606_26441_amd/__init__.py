@@ -22,13 +22,13 @@ LIB_PATH = os.path.join(_HERE, "libgpusparse.so")
 GS_OK, GS_EINVAL, GS_ENOMEM, GS_EHIP, GS_ECAPACITY, GS_EUNSUPPORTED, GS_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 GS_FP32, GS_BF16, GS_U8 = 0, 1, 2
 GS_KEEP_FORWARD, GS_KEEP_DOC_IDS = 1, 2
-GS_KERNEL_AUTO, GS_KERNEL_TILED, GS_KERNEL_ATOMIC, GS_KERNEL_DOCPAR, GS_KERNEL_SHARED = 0, 1, 2, 3, 4
+GS_KERNEL_AUTO, GS_KERNEL_TILED, GS_KERNEL_ATOMIC, GS_KERNEL_DOCPAR, GS_KERNEL_SHARED, GS_KERNEL_GROUP = 0, 1, 2, 3, 4, 5
 GS_MAX_K = 4096
 GS_MAX_QUERY_NNZ = 256
 
 PRECISIONS = {"fp32": GS_FP32, "bf16": GS_BF16, "u8": GS_U8}
 KERNELS = {"auto": GS_KERNEL_AUTO, "tiled": GS_KERNEL_TILED, "atomic": GS_KERNEL_ATOMIC,
-           "docpar": GS_KERNEL_DOCPAR, "shared": GS_KERNEL_SHARED}
+           "docpar": GS_KERNEL_DOCPAR, "shared": GS_KERNEL_SHARED, "group": GS_KERNEL_GROUP}
 SCORE_DTYPES = {GS_FP32: torch.float32, GS_BF16: torch.float64, GS_U8: torch.int32}
 
 
@@ -44,7 +44,8 @@ _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "HIP error"
 
 class SearchOpts(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("query_tile", ctypes.c_int32), ("tile_docs", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("no_fused_filter", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("chunk", ctypes.c_int32), ("no_fused_filter", ctypes.c_int32), ("prune", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -76,6 +77,8 @@ def _load() -> ctypes.CDLL:
     lib.gs_status_string.argtypes = [i32]
     lib.gs_status_string.restype = ctypes.c_char_p
     lib.gs_last_error.restype = ctypes.c_char_p
+    lib.gs_debug_fail_alloc.argtypes = [i64]
+    lib.gs_debug_fail_alloc.restype = i32
     lib.gs_build_index.argtypes = [vp, i64, vp, vp, i64, i32, i32, u32, vp, P(vp)]
     lib.gs_build_index.restype = i32
     lib.gs_index_info.argtypes = [vp, P(IndexInfo)]
@@ -156,11 +159,12 @@ def _stream_ptr(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_opts(kernel="auto", query_tile=0, tile_docs=0, chunk=0, fused_filter=True) -> SearchOpts:
+def make_opts(kernel="auto", query_tile=0, tile_docs=0, chunk=0, fused_filter=True, prune=False) -> SearchOpts:
     o = SearchOpts()
     o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.query_tile, o.tile_docs, o.chunk = int(query_tile), int(tile_docs), int(chunk)
     o.no_fused_filter = 0 if fused_filter else 1
+    o.prune = 1 if prune else 0
     return o
 
 
@@ -384,7 +388,8 @@ class Batch:
 
     def diagnostics(self) -> np.ndarray:
         """[n_queries, 8]: candidates, refinement passes, bf16 band size, overflow flag, rows scored
-        again (0 no, 1 fused-filtering fallback, 2 wide range: fp64 pass), fused filtering used, 0, 0."""
+        again (0 no, 1 fused-filtering fallback, 2 wide range: fp64 pass), fused filtering used,
+        64-posting blocks skipped by pruning, 0."""
         out = np.zeros((self.n_queries, 8), dtype=np.int32)
         _check(lib.gs_batch_diagnostics(self._h, out.ctypes.data), "gs_batch_diagnostics")
         return out
@@ -486,6 +491,11 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def debug_fail_alloc(n: int):
+    """Test hook: the library's allocation after n more succeeds fails once (n < 0 disarms)."""
+    lib.gs_debug_fail_alloc(int(n))
 
 
 def version() -> str:

@@ -23,6 +23,35 @@ using namespace gs;
 namespace gs {
 thread_local const char* g_failed_launch = "";
 int32_t set_error(int32_t code, const std::string& msg);
+
+namespace {
+// fault injection for tests: allocations left before one fails (-1: none fails)
+std::atomic<int64_t> g_alloc_countdown{-1};
+
+bool inject_alloc_failure() {
+    int64_t v = g_alloc_countdown.load();
+    while (v >= 0) {
+        if (g_alloc_countdown.compare_exchange_weak(v, v - 1)) return v == 0;
+    }
+    return false;
+}
+}  // namespace
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    if (inject_alloc_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+hipError_t pinned_malloc(void** p, size_t bytes) {
+    if (inject_alloc_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
 }  // namespace gs
 
 namespace {
@@ -392,7 +421,8 @@ struct gs_index_s {
 // whole on every update), then the per-term arrays (copied up to the terms in use).
 struct BatchLayout {
     size_t rp = 0, k = 0, fs = 0, delta = 0, scale = 0, err = 0, wide = 0, work = 0, diag = 0, head = 0;
-    size_t term = 0, w = 0, w8 = 0, fx = 0, total = 0;
+    size_t gcount = 0, gmember = 0, grow = 0;
+    size_t term = 0, w = 0, w8 = 0, fx = 0, ubcum = 0, gterm = 0, gwfx = 0, gw8 = 0, total = 0;
     BatchLayout(size_t nq, size_t nz) {
         size_t at = 0;
         auto take = [&](size_t bytes) {
@@ -409,11 +439,18 @@ struct BatchLayout {
         wide = take(nq * 8);
         work = take(nq * 8);
         diag = take(nq * kDiagWords * 4);
+        gcount = take(4);
+        gmember = take((nq + kGroupMax) * 4);
+        grow = take((nq + 2) * 4);
         head = at;
         term = take(nz * 4);
         w = take(nz * 4);
         w8 = take(nz * 4);
         fx = take(nz * 8);
+        ubcum = take(nz * 8);
+        gterm = take(nz * 4);
+        gwfx = take(nz * kGroupMax * 4);
+        gw8 = take(nz * kGroupMax * 4);
         total = at;
     }
 };
@@ -449,7 +486,7 @@ int32_t dev_upload(std::vector<void*>& allocs, size_t& bytes, const T* host, siz
     if (n == 0) n = 1;  // keep a valid pointer for empty arrays
     n += slack;         // zeroed entries past the end
     void* p = nullptr;
-    GS_HIP(hipMalloc(&p, n * sizeof(T)));
+    GS_HIP(dev_malloc(&p, n * sizeof(T)));
     allocs.push_back(p);
     bytes += n * sizeof(T);
     if (host && copy) GS_HIP(hipMemcpyAsync(p, host, copy * sizeof(T), hipMemcpyHostToDevice, s));
@@ -595,6 +632,11 @@ const char* gs_status_string(int32_t s) {
 }
 
 const char* gs_last_error(void) { return g_err.c_str(); }
+
+int32_t gs_debug_fail_alloc(int64_t n) {
+    g_alloc_countdown.store(n < 0 ? -1 : n);
+    return GS_OK;
+}
 
 int32_t gs_layout_host(const int64_t* row_ptr, int64_t n_docs, const int32_t* term_ids, const float* weights,
                        int64_t nnz, int32_t vocab_size, int32_t precision, int64_t* out_padded_nnz, int64_t* term_off,
@@ -861,8 +903,8 @@ int32_t gs_batch_reserve(gs_index ix, int32_t max_queries, int64_t max_nnz, int3
     b->lay = BatchLayout(nq, nz);
     const BatchLayout& L = b->lay;
     {
-        hipError_t e = hipMalloc((void**)&b->dmem, L.total);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&b->stage, L.total, hipHostMallocDefault);
+        hipError_t e = dev_malloc((void**)&b->dmem, L.total);
+        if (e == hipSuccess) e = pinned_malloc((void**)&b->stage, L.total);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
         if (e != hipSuccess)
             return done(fail(e == hipErrorOutOfMemory ? GS_ENOMEM : GS_EHIP,
@@ -877,12 +919,19 @@ int32_t gs_batch_reserve(gs_index ix, int32_t max_queries, int64_t max_nnz, int3
     d.q_w = (const float*)(m + L.w);
     d.q_w8 = (const int32_t*)(m + L.w8);
     d.q_fx = (const double*)(m + L.fx);
+    d.q_ub_cum = (const unsigned long long*)(m + L.ubcum);
     d.k = (const int32_t*)(m + L.k);
     d.first_shift = (const int32_t*)(m + L.fs);
     d.delta = (const float*)(m + L.delta);
     d.q_scale = (const double*)(m + L.scale);
     d.q_abs_err = (const double*)(m + L.err);
     d.q_wide_lim = (const double*)(m + L.wide);
+    d.g_count = (const int32_t*)(m + L.gcount);
+    d.g_member = (const int32_t*)(m + L.gmember);
+    d.g_row = (const int32_t*)(m + L.grow);
+    d.g_term = (const int32_t*)(m + L.gterm);
+    d.g_wq = (const float*)(m + L.gwfx);
+    d.g_w8 = (const int32_t*)(m + L.gw8);
     d.q_work = (const int64_t*)(m + L.work);
     b->diag = (int32_t*)(m + L.diag);
     // an empty batch until the first update: every slot is a query with no terms and k = 0
@@ -930,6 +979,7 @@ int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, co
     int64_t* qwork = (int64_t*)(h + L.work);
     int32_t* w8 = (int32_t*)(h + L.w8);
     double* qfx = (double*)(h + L.fx);
+    unsigned long long* qub = (unsigned long long*)(h + L.ubcum);
     // slots past n_queries become empty queries with k = 0 (no work, padding-only rows)
     for (int32_t q = 0; q <= cap; q++) rp[q] = q <= n_queries ? (q_row_ptr ? q_row_ptr[q] : 0) : q_nnz;
     for (int32_t q = 0; q < cap; q++) kk[q] = q < n_queries ? k[q] : 0;
@@ -964,8 +1014,75 @@ int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, co
         qerr[q] = fp.abs_err;
         qwide[q] = fp.wide_lim;
         for (int64_t j = rp[q]; j < rp[q + 1]; j++) qfx[j] = std::ldexp((double)r.w[j], fp.F);
+        // Block-max pruning: each term's upper bound on its product with any doc (fixed-point
+        // units: the largest stored weight times w_q 2^F, rounded up, plus one for the product's
+        // rounding; uint8: the exact integer product), then per term the sum of the bounds of
+        // the terms up to it in ascending order of bound (ties by position).
+        {
+            std::vector<std::pair<unsigned long long, int64_t>> ub;
+            ub.reserve((size_t)m);
+            for (int64_t j = rp[q]; j < rp[q + 1]; j++) {
+                const double tm = (double)ix->term_max[(size_t)r.term[j]];
+                const unsigned long long u = ix->precision == kU8
+                                                 ? (unsigned long long)w8[j] * (unsigned long long)tm
+                                                 : (unsigned long long)std::ceil(qfx[j] * tm) + 1ull;
+                ub.emplace_back(u, j);
+            }
+            std::sort(ub.begin(), ub.end());
+            unsigned long long run = 0;
+            for (const auto& e : ub) {
+                run += e.first;
+                qub[e.second] = run;
+            }
+        }
         // bf16 form: relative error of a stored weight (2^-8) and of the fp32 score (2^-24, with margin)
         delta[q] = (float)(((1.0 + std::ldexp(1.0, -8)) * (1.0 + std::ldexp(1.0, -23)) - 1.0) * (1.0 + 1e-6));
+    }
+    // Groups of the group kernel: the queries with k > 0 by descending work (ties by index),
+    // G consecutive ones per group, and per group the ascending union of the members' terms
+    // with each member's weight w_q (0 where it lacks the term; the kernel scales it by 2^F of
+    // the member). Terms are ascending per query.
+    const int G = 2;  // the group kernel's group size, every precision
+    int32_t* gcnt = (int32_t*)(h + L.gcount);
+    int32_t* gmem = (int32_t*)(h + L.gmember);
+    int32_t* grow = (int32_t*)(h + L.grow);
+    int32_t* gterm = (int32_t*)(h + L.gterm);
+    float* gwq = (float*)(h + L.gwfx);
+    int32_t* gw8 = (int32_t*)(h + L.gw8);
+    int64_t n_union = 0;
+    {
+        std::vector<int32_t> ord;
+        for (int32_t q = 0; q < n_queries; q++)
+            if (kk[q] > 0) ord.push_back(q);
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return qwork[a] > qwork[b]; });
+        const int32_t ng = (int32_t)((ord.size() + G - 1) / G);
+        *gcnt = ng;
+        grow[0] = 0;
+        for (int32_t g = 0; g < ng; g++) {
+            int64_t at[kGroupMax], end[kGroupMax];
+            for (int m = 0; m < G; m++) {
+                const size_t i = (size_t)g * G + m;
+                const int32_t q = i < ord.size() ? ord[i] : -1;
+                gmem[g * G + m] = q;
+                at[m] = q >= 0 ? rp[q] : 0;
+                end[m] = q >= 0 ? rp[q + 1] : 0;
+            }
+            for (;;) {  // merge of the members' ascending term lists
+                int32_t t = INT32_MAX;
+                for (int m = 0; m < G; m++)
+                    if (at[m] < end[m]) t = std::min(t, r.term[at[m]]);
+                if (t == INT32_MAX) break;
+                gterm[n_union] = t;
+                for (int m = 0; m < G; m++) {
+                    const bool has = at[m] < end[m] && r.term[at[m]] == t;
+                    gwq[n_union * G + m] = has ? r.w[at[m]] : 0.0f;
+                    gw8[n_union * G + m] = has ? w8[at[m]] : 0;
+                    if (has) at[m]++;
+                }
+                n_union++;
+            }
+            grow[g + 1] = (int32_t)n_union;
+        }
     }
     // copies on the caller's stream, ordered after the searches already enqueued on it
     hipStream_t s = (hipStream_t)hip_stream;
@@ -977,6 +1094,10 @@ int32_t batch_update(gs_batch b, const int64_t* q_row_ptr, int32_t n_queries, co
     if (e == hipSuccess) e = up(L.w, (size_t)q_nnz * 4);
     if (e == hipSuccess) e = up(L.w8, (size_t)q_nnz * 4);
     if (e == hipSuccess) e = up(L.fx, (size_t)q_nnz * 8);
+    if (e == hipSuccess) e = up(L.ubcum, (size_t)q_nnz * 8);
+    if (e == hipSuccess) e = up(L.gterm, (size_t)n_union * 4);
+    if (e == hipSuccess) e = up(L.gwfx, (size_t)n_union * G * 4);
+    if (e == hipSuccess) e = up(L.gw8, (size_t)n_union * G * 4);
     if (e == hipSuccess) e = hipEventRecord(b->copied, s);
     if (e == hipSuccess) {
         b->copy_pending = true;
@@ -1031,11 +1152,12 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
     so->chunk = 1024;  // measured fastest for both doc-tiled forms at every tile size
     so->seed_stride = 1;  // fused filtering wanted (the stride itself is chosen per search)
     if (!o) return GS_OK;
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < 2; i++)
         if (o->reserved[i] != 0) return fail(GS_EINVAL, "reserved option fields must be 0");
+    if (o->prune != 0 && o->prune != 1) return fail(GS_EINVAL, "prune must be 0 or 1");
     if (o->no_fused_filter != 0 && o->no_fused_filter != 1) return fail(GS_EINVAL, "no_fused_filter must be 0 or 1");
     if (o->no_fused_filter) so->seed_stride = 0;
-    if (o->kernel < GS_KERNEL_AUTO || o->kernel > GS_KERNEL_SHARED) return fail(GS_EINVAL, "unknown kernel");
+    if (o->kernel < GS_KERNEL_AUTO || o->kernel > GS_KERNEL_GROUP) return fail(GS_EINVAL, "unknown kernel");
     if (o->kernel != GS_KERNEL_AUTO) so->kernel = o->kernel;
     if (so->kernel == GS_KERNEL_DOCPAR && !(ix->flags & GS_KEEP_FORWARD))
         return fail(GS_EUNSUPPORTED, "document-parallel kernel needs an index built with GS_KEEP_FORWARD");
@@ -1055,6 +1177,22 @@ static int32_t resolve_opts(gs_index ix, const gs_search_opts* o, ScoreOpts* so)
         case 0: break;
         case 64: case 128: case 256: case 512: case 1024: so->chunk = o->chunk; break;
         default: return fail(GS_EINVAL, "chunk must be 0, 64, 128, 256, 512 or 1024");
+    }
+    if (o->prune) {
+        const int def_shift = ix->precision == kFP32 ? 13 : 14;
+        if (so->kernel != GS_KERNEL_TILED || ix->precision == kBF16 || so->tile_shift != def_shift ||
+            so->chunk != 1024)
+            return fail(GS_EUNSUPPORTED,
+                        "pruning needs GS_KERNEL_TILED, fp32 or uint8 weights, the default tile and chunk 1024");
+        so->prune = 1;
+    }
+    if (so->kernel == GS_KERNEL_GROUP) {
+        if (o->tile_docs != 0 && o->tile_docs != (1 << kGroupTileShift))
+            return fail(GS_EUNSUPPORTED, "the group kernel works on 8192-doc tiles");
+        // measured: chunks of 1024 for uint8; the fixed-point forms spill registers at 1024
+        if (o->chunk == 0) so->chunk = ix->precision == kU8 ? 1024 : 512;
+        if (so->chunk < 256) return fail(GS_EUNSUPPORTED, "the group kernel takes chunks of 256, 512 or 1024");
+        so->tile_shift = kGroupTileShift;
     }
     return GS_OK;
 }
@@ -1123,8 +1261,11 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, const Workspace& ws,
     // The seed tiles should hold several times k documents: stride 8 up to k = 1024, 4 up to
     // 2048, else off; it needs at least two seed tiles. It adds five launches to a search,
     // which a few queries' row scans do not repay: searches of fewer than 32 queries scan.
+    // the group kernel's groups span the whole batch: with query tiles it gives way to the
+    // shared-traversal kernel
+    if (so.kernel == GS_KERNEL_GROUP && qt < nq) so.kernel = GS_KERNEL_SHARED;
     {
-        const bool tiled = so.kernel == GS_KERNEL_TILED || so.kernel == GS_KERNEL_SHARED;
+        const bool tiled = so.kernel == GS_KERNEL_TILED || so.kernel == GS_KERNEL_SHARED || so.kernel == GS_KERNEL_GROUP;
         const int64_t n_tiles = (ix->n_docs + (1ll << so.tile_shift) - 1) >> so.tile_shift;
         int stride = b->k_max <= 1024 ? 8 : (b->k_max <= 2048 ? 4 : 0);
         if (!tiled || so.seed_stride == 0 || n_tiles < 2 * (int64_t)stride || nq < 32) stride = 0;
@@ -1136,17 +1277,20 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, const Workspace& ws,
         const int32_t n = std::min(qt, nq - q0);
         hipError_t e = launch_clear(ws, n, s);
         if (e == hipSuccess && ix->n_docs > 0) {
-            if (so.seed_stride == 0 || (so.kernel != GS_KERNEL_TILED && so.kernel != GS_KERNEL_SHARED)) {
+            const bool group = so.kernel == GS_KERNEL_GROUP;
+            if (so.seed_stride == 0 || so.kernel == GS_KERNEL_ATOMIC || so.kernel == GS_KERNEL_DOCPAR) {
                 SpanRecorder rec(timing ? 0 : -1, s);
                 if (so.kernel == GS_KERNEL_ATOMIC) e = launch_score_atomic(ix->dev, b->dev, q0, n, so, ws, s);
                 else if (so.kernel == GS_KERNEL_DOCPAR) e = launch_score_docpar(ix->dev, b->dev, q0, n, so, ws, s);
+                else if (group) e = launch_score_group(ix->dev, b->dev, so, ws, s, 0);
                 else e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s);
                 rec.end(s);
             } else {
                 // fused filtering: seed tiles, their bound (selection work), then the other tiles
                 {
                     SpanRecorder rec(timing ? 0 : -1, s, false);
-                    e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 1);
+                    e = group ? launch_score_group(ix->dev, b->dev, so, ws, s, 1)
+                              : launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 1);
                     rec.end(s);
                 }
                 if (e == hipSuccess) {
@@ -1156,7 +1300,8 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, const Workspace& ws,
                 }
                 if (e == hipSuccess) {
                     SpanRecorder rec(timing ? 0 : -1, s);
-                    e = launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 2);
+                    e = group ? launch_score_group(ix->dev, b->dev, so, ws, s, 2)
+                              : launch_score_tiled(ix->dev, b->dev, q0, n, so, ws, s, 2);
                     rec.end(s);
                 }
             }
@@ -1166,7 +1311,8 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, const Workspace& ws,
             // Between the two first-digit selection passes: the rows of the listed queries.
             // Fused fp32 / uint8 queries that fell back get their non-seed tiles scored (phase 3);
             // fixed-point queries found wide range get every tile scored in fp64 (phase 4).
-            const bool doc_tiled = so.kernel == GS_KERNEL_TILED || so.kernel == GS_KERNEL_SHARED;
+            const bool doc_tiled =
+                so.kernel == GS_KERNEL_TILED || so.kernel == GS_KERNEL_SHARED || so.kernel == GS_KERNEL_GROUP;
             const bool fixed = doc_tiled && ix->precision != kU8;
             const bool phase3 = so.seed_stride > 0 && ix->precision != kBF16;
             const int acc = ix->precision == kU8 ? kAccInteger : (doc_tiled ? kAccFixed : kAccFloat);
@@ -1352,6 +1498,13 @@ int32_t gs_autotune(gs_index ix, gs_batch b, void* workspace, size_t workspace_b
                 o.chunk = c;
                 cand.push_back(o);
             }
+    for (int c : {256, 512, 1024}) {  // the group kernel: 8192-doc tiles
+        gs_search_opts o{};
+        o.kernel = GS_KERNEL_GROUP;
+        o.tile_docs = 1 << kGroupTileShift;
+        o.chunk = c;
+        cand.push_back(o);
+    }
     DeviceGuard g(ix->device);
     hipStream_t s = (hipStream_t)hip_stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;

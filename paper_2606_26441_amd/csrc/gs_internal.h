@@ -29,6 +29,12 @@ constexpr int kFusedCap = 24576;      // of which appended while scoring (fused 
 constexpr int kRefinePasses = 6;      // enough to resolve any 64-bit composite key
 constexpr int kFirstShiftFloat = 52;  // first digit of a float key: bits 30..20
 constexpr int kDiagWords = 8;         // per-query words of gs_batch_diagnostics
+// Group kernel (GS_KERNEL_GROUP): 8192-doc tiles, at most 4 queries per group, so at most
+// 4 x 256 distinct terms per group.
+constexpr int kGroupTileShift = 13;
+constexpr int kGroupMax = 4;
+constexpr int kGroupMaxTerms = kGroupMax * kMaxQueryNnz;
+constexpr int kGroupChunkTab = 1024;  // chunk table entries of a group work item (two workgroups per CU keep fitting the LDS)
 // Fixed scratch array of the allocation-free search (gs_search_batch_noalloc): one per
 // device, 128 MiB (a one-query workspace for collections up to about 33M documents).
 constexpr size_t kScratchBytes = (size_t)128 << 20;
@@ -37,6 +43,11 @@ enum Precision { kFP32 = 0, kBF16 = 1, kU8 = 2 };
 
 // Record the message returned by gs_last_error() on this thread; returns code.
 int32_t set_error(int32_t code, const std::string& msg);
+
+// Device and pinned host allocations of the library go through these, so that a test can
+// make the n-th one fail (gs_debug_fail_alloc) and check the GS_ENOMEM paths.
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t pinned_malloc(void** p, size_t bytes);
 
 // Name of the kernel whose launch failed last on this thread (for error messages).
 extern thread_local const char* g_failed_launch;
@@ -99,6 +110,21 @@ struct DevBatch {
     // scored again with fp64 accumulation; 0 when the bound holds for every positive score.
     const double* q_wide_lim;
     const int64_t* q_work;     // [n] postings of the query's terms (work estimate)
+    // Block-max pruning (opt-in): per query term, the sum of the upper bounds of the query's
+    // terms (w_q times the term's largest stored weight, in fixed-point units or as an exact
+    // uint8 product) taken in ascending order of bound, up to and including this term.
+    const unsigned long long* q_ub_cum;  // [q_nnz]
+    // Groups of the group kernel (built on the host at each update): the queries with k > 0
+    // by descending work, G consecutive per group (G = 2 for fp32, 4 for bf16 and uint8);
+    // per group the ascending union of its members' terms with each member's weight
+    // (w_q, scaled by the member's 2^F in the kernel, or the uint8 impact; 0 where the member
+    // lacks the term).
+    const int32_t* g_count;    // [1] number of groups
+    const int32_t* g_member;   // [groups * G] query of each member (-1: none)
+    const int32_t* g_row;      // [groups + 1] start of each group's union terms
+    const int32_t* g_term;     // [union terms]
+    const float* g_wq;         // [union terms * G] (fp32, bf16)
+    const int32_t* g_w8;       // [union terms * G] (uint8)
 };
 
 // Per-query selection state in the workspace.
@@ -122,7 +148,7 @@ struct SelState {
     // 1: fell back from fused filtering after its non-seed rows were left unwritten (score
     // them again, fixed point); 2: wide range (score every tile again, fp64 accumulation)
     int32_t rescore;
-    int32_t pad_;
+    int32_t pruned;             // 64-posting blocks skipped by block-max pruning
 };
 
 // Workspace carve-up for a tile of qt queries.
@@ -154,6 +180,7 @@ struct ScoreOpts {
     int tile_shift;   // doc tile of the TILED/SHARED kernels = 1 << tile_shift docs
     int chunk;        // postings per work item
     int seed_stride = 0;  // fused candidate filtering: every seed_stride-th doc tile seeds the bound (0: off)
+    int prune = 0;        // block-max pruning of the non-seed tiles (TILED, fp32 and uint8)
 };
 
 // Doc tiles of a scoring launch: phase 0 all tiles, phase 1 the seed tiles
@@ -191,6 +218,9 @@ const int32_t* batch_diag(const struct ::gs_batch_s* b);
 hipError_t launch_clear(const Workspace& ws, int32_t qt, hipStream_t s);
 hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt,
                               const ScoreOpts& o, const Workspace& ws, hipStream_t s, int phase = 0);
+// group kernel (GS_KERNEL_GROUP): phases 0, 1 and 2 of a search whose queries form one tile
+hipError_t launch_score_group(const DevIndex& ix, const DevBatch& qb, const ScoreOpts& o, const Workspace& ws,
+                              hipStream_t s, int phase);
 // fp64-accumulating pass over every doc tile for the queries listed as wide range
 // (fp32, bf16); a no-op when none is listed
 hipError_t launch_score_wide(const DevIndex& ix, const DevBatch& qb, int32_t q0, const Workspace& ws, hipStream_t s);

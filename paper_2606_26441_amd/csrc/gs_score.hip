@@ -259,6 +259,15 @@ constexpr int acc_form() {
     return W ? kAccF64 : (P == kFP32 ? kAccFx64 : (P == kBF16 ? kAccFx32 : kAccInt));
 }
 
+// Queries per work item of the group kernel. Two: 64 KiB of 32-bit accumulators over
+// 8192 docs (bf16, uint8), so that two workgroups share a CU and one accumulates while the
+// other flushes; 128 KiB of 64-bit ones (fp32). (Four queries with 32-bit sums, 128 KiB and
+// one workgroup per CU, measured slower.)
+template <int P>
+constexpr int group_size() {
+    return 2;
+}
+
 // Word 3 of a raw buffer descriptor on the gfx9 family (gfx950 included): no stride,
 // no swizzle, 32-bit data format; the hardware range-checks each lane's byte offset
 // against the record count and returns 0 past it.
@@ -275,6 +284,7 @@ struct TileShared {
     uint32_t seg_q8[kMaxQueryNnz]; // uint8 query impact
     uint16_t seg_edge[kMaxQueryNnz];
     unsigned long long dmask[kMaxQueryNnz / kWave];  // dense terms per wavefront of the setup
+    unsigned long long wmax[kMaxQueryNnz / kWave];   // pruning: largest bound sum per wavefront
 };
 static_assert(kMaxQueryNnz <= 512 && kMaxQueryNnz % kWave == 0, "segment setup: one thread per query term");
 
@@ -313,7 +323,16 @@ __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* ta
 // it pays only where the kernel waits on HBM (the per-query kernel with fp32 or
 // bf16 weights), not where it is bound by instruction issue (shared traversal,
 // uint8 weights). W: the wide-range pass (fp64 products w_q * w_d, fp64 sums).
-template <int P, int TS, int CH, bool DB, bool W = false>
+// PR: block-max pruning (MaxScore over 64-posting blocks) in the non-seed tiles of a query
+// with a seed bound, for fp32 and uint8 weights (no byte doc ids, DB false). The query's
+// terms with the smallest bounds w_q * maxw, as long as their bounds sum to less than the
+// bound's raw score t_lo, are non-essential: no doc that holds none of the others can be a
+// candidate. The essential terms are scored first; then each 64-doc group of the tile gets
+// its largest partial sum, and a block of a non-essential term is skipped (not even read)
+// when every doc it can hold has partial sum + the non-essential bounds' sum below t_lo. A
+// doc of a skipped block can then not reach the bound, so it is no candidate, and every
+// candidate's sum is complete: the result is exact.
+template <int P, int TS, int CH, bool DB, bool W = false, bool PR = false>
 __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& qb, int32_t q0, int64_t tile, int ql,
                                            uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
                                            uint32_t* lds, TileShared& sh, int phase, SelState* state,
@@ -344,22 +363,54 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     const int nq = (int)(qb.q_row_ptr[q + 1] - qa);
     const int64_t g0 = tile << GPT;
     const int64_t g1 = min(g0 + (int64_t)(1 << GPT), ix.n_grains);
+    static_assert(!(PR && DB), "pruning reads 2-byte doc ids");
+    static_assert(!PR || (P != kBF16 && !W), "pruning: fp32 and uint8 fixed-point or integer sums");
+    // Pruning applies to the non-seed tiles of a query whose seed bound is set; t_lo is the
+    // bound's score as a raw sum (no sum below it can give a candidate, see flush_tile).
+    bool prune_item = false;
+    unsigned long long t_lo = 0;
+    if constexpr (PR) {
+        const SelState* stq = state + ql;
+        if (phase == 2 && stq->fused == 1) {
+            const uint32_t sb = (uint32_t)(stq->bound >> 32);
+            if constexpr (P == kU8) t_lo = sb;
+            else t_lo = (unsigned long long)fmax(0.0, floor((double)__uint_as_float(sb) * (1.0 - 0x1p-22) / qb.q_scale[q]));
+            prune_item = t_lo > 0;
+        }
+    }
     // One thread per query term. Dense terms take the first segment slots (in query
-    // order), so their chunks come first and run in the byte-offset loop.
+    // order), so their chunks come first and run in the byte-offset loop. With pruning the
+    // essential terms come first (exact segments) and the non-essential ones after them
+    // (whole 64-posting blocks, each skipped or read).
     const int t = tid;
     const bool live = t < nq;
     int term = 0, a = 0, b = 0;
-    bool dense = false;
+    bool dense = false;  // first loop: byte doc ids (DB), or the essential terms (PR)
+    unsigned long long ub_cum = 0;
     if (live) {
         term = qb.q_term[qa + t];
         const int32_t* row = ix.tile_off + (int64_t)term * (ix.n_grains + 1);
         a = row[g0];
         b = row[g1];
         dense = DB && ix.term_dense[term] != 0 && b > a;
+        if constexpr (PR) {
+            ub_cum = qb.q_ub_cum[qa + t];
+            dense = !prune_item || !(ub_cum < t_lo);
+        }
     }
     if (t < kMaxQueryNnz) {
         const unsigned long long m = __ballot(live && dense);
         if (lane == 0) sh.dmask[wave] = m;
+        if constexpr (PR) {
+            // the bound sum of the non-essential terms: the largest cumulative bound among them
+            unsigned long long v = (live && !dense) ? ub_cum : 0ull;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const unsigned long long o = __shfl_xor(v, d, kWave);
+                v = o > v ? o : v;
+            }
+            if (lane == 0) sh.wmax[wave] = v;
+        }
     }
     __syncthreads();
     if (live) {
@@ -383,7 +434,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
             zero_weight = q8 == 0u;
         }
         int beg = a, len = b - a, edge = 0;
-        if (dense) {  // whole blocks: lists start 64-aligned and are padded to 64
+        if (PR ? (!dense && b > a) : dense) {  // whole blocks: lists start 64-aligned and are padded to 64
             beg = a & ~(kBlock - 1);
             const int end = (b + kBlock - 1) & ~(kBlock - 1);
             len = end - beg;
@@ -440,7 +491,18 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         uint32_t w[U];    // stored weight as fp32 bits, or the uint8 impact
         int32_t blk;      // (dense) lane u < U: first doc of the chunk's block u
         int seg, n, lo;   // postings [lo, n) of the chunk are the segment's (lo > 0: first slot only)
+        uint32_t skip;    // (pruned blocks) bit u: block u of the chunk is skipped
     };
+    // Chunk forms: 0 exact segment, 2-byte ids; 1 dense term, whole blocks, 1-byte ids;
+    // 2 non-essential term under pruning, whole blocks, 2-byte ids, skipped blocks not read.
+    using FExact = std::integral_constant<int, 0>;
+    using FDense = std::integral_constant<int, 1>;
+    using FPrune = std::integral_constant<int, 2>;
+    // pruning: per 64-doc group of the tile, the largest sum of the essential terms (in the
+    // histogram area's last 2 KiB, which the chunk table leaves free for pruned items)
+    unsigned long long* gmax = reinterpret_cast<unsigned long long*>(hist) + (kHistBins / 2 - 256);
+    unsigned long long u_n = 0;  // the bound sum of the non-essential terms
+    const int tbase = __builtin_amdgcn_readfirstlane((int)base);
     using WT = std::conditional_t<P == kU8, uint8_t, std::conditional_t<P == kBF16, uint16_t, uint32_t>>;
     // Loads are straight-line (no branch around them, so the compiler can wait for
     // the older chunk only): lanes past the end of a chunk read 0, and an empty slot
@@ -449,29 +511,54 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // The chunk lookup is branch-free with the chunk table (an invalid slot looks up
     // chunk 0 and gets length 0). A dense chunk covers whole blocks: it reads 1-byte
     // distances, plus one block base per 64 postings.
-    auto load = [&](auto use_tab, auto dense_form, int c, Chunk& k, bool valid) {
-        constexpr bool DENSE = decltype(dense_form)::value;
+    auto load = [&](auto use_tab, auto form, int c, Chunk& k, bool valid) {
+        constexpr bool DENSE = decltype(form)::value == 1;
+        constexpr bool PRUNED = decltype(form)::value == 2;
         int64_t p0 = 0;
         int n = 0, off = 0;
         chunk_at<decltype(use_tab)::value>(sh, tab, nq, valid ? c : 0, CH, &k.seg, &p0, &n, &off);
-        if constexpr (DENSE) {
+        k.skip = 0u;
+        if constexpr (DENSE || PRUNED) {
             const int edge = __builtin_amdgcn_readfirstlane((int)sh.seg_edge[k.seg]);
             const int real_end = sh.seg_len[k.seg] - (edge >> 8) - off;
             k.lo = off == 0 ? (edge & 0xFF) : 0;
             k.n = valid ? min(n, real_end) : 0;
-            // one register for the chunk's block bases (lane u holds block u); a slot takes
-            // its base with a lane read, which keeps scalar registers free
-            const int nblk = (n + kBlock - 1) >> 6;
-            k.blk = ix.blk_first[(p0 >> 6) + min(lane, max(nblk - 1, 0))];
         } else {
             k.lo = 0;
             k.n = valid ? n : 0;
+        }
+        const int nblk = (n + kBlock - 1) >> 6;
+        if constexpr (DENSE) {
+            // one register for the chunk's block bases (lane u holds block u); a slot takes
+            // its base with a lane read, which keeps scalar registers free
+            k.blk = ix.blk_first[(p0 >> 6) + min(lane, max(nblk - 1, 0))];
+        }
+        if constexpr (PRUNED) {
+            // lane u < nblk decides block u: the docs it can hold are [its first doc, the next
+            // block's first doc) inside the segment, the tile's end for the segment's last
+            // block, clipped to the tile; it is skipped when every 64-doc group they touch has
+            // essential sum + u_n below t_lo
+            bool sk = false;
+            if (valid && lane < nblk) {
+                const int64_t blk = (p0 >> 6) + lane;
+                const int64_t seg_end_blk = (sh.seg_beg[k.seg] + sh.seg_len[k.seg]) >> 6;
+                const int first = ix.blk_first[blk];
+                const int last = blk + 1 < seg_end_blk ? ix.blk_first[blk + 1] - 1 : tbase + tile_n - 1;
+                const int lo = max(first - tbase, 0), hi = min(last - tbase, tile_n - 1);
+                unsigned long long m = 0;
+                for (int gi = lo >> 6; gi <= (hi >> 6); gi++) m = gmax[gi] > m ? gmax[gi] : m;
+                sk = m + u_n < t_lo;
+            }
+            k.skip = (uint32_t)__ballot(sk);
+            if (k.skip != 0u && lane == 0) atomicAdd(&state[ql].pruned, __popc(k.skip));
         }
         // Buffer loads over the chunk: the descriptor's record count is the chunk's bytes,
         // so lanes past its end read 0 without a clamp, and slot u's offset is the
         // instruction's immediate (one lane-offset register per chunk).
         const int nrec = valid ? n : 0;
         const void* lb = DENSE ? static_cast<const void*>(ix.post_b8 + p0) : static_cast<const void*>(ix.post_lo + p0);
+        // a skipped block's lanes get an offset past the record count: the hardware reads nothing
+        auto far = [&](int u) { return PRUNED && ((k.skip >> u) & 1u) ? (1 << 30) : 0; };
         const void* wb = static_cast<const void*>(reinterpret_cast<const WT*>(ix.post_w) + p0);
         const __amdgpu_buffer_rsrc_t rid =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(lb), (short)0, nrec * (DENSE ? 1 : 2), kRawBufferWord3);
@@ -486,11 +573,11 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
 #pragma unroll
         for (int u = 0; u < U; u++) {
             if constexpr (DENSE) k.doc[u] = __builtin_amdgcn_raw_buffer_load_b8(rid, vid + u * kWave, 0, 0);
-            else k.doc[u] = __builtin_amdgcn_raw_buffer_load_b16(rid, vid + u * kWave * 2, 0, 0);
+            else k.doc[u] = __builtin_amdgcn_raw_buffer_load_b16(rid, vid + far(u) + u * kWave * 2, 0, 0);
             uint32_t wv;
-            if constexpr (sizeof(WT) == 4) wv = __builtin_amdgcn_raw_buffer_load_b32(rw, vw + u * kWave * 4, 0, 0);
-            else if constexpr (sizeof(WT) == 2) wv = __builtin_amdgcn_raw_buffer_load_b16(rw, vw + u * kWave * 2, 0, 0);
-            else wv = __builtin_amdgcn_raw_buffer_load_b8(rw, vw + u * kWave, 0, 0);
+            if constexpr (sizeof(WT) == 4) wv = __builtin_amdgcn_raw_buffer_load_b32(rw, vw + far(u) + u * kWave * 4, 0, 0);
+            else if constexpr (sizeof(WT) == 2) wv = __builtin_amdgcn_raw_buffer_load_b16(rw, vw + far(u) + u * kWave * 2, 0, 0);
+            else wv = __builtin_amdgcn_raw_buffer_load_b8(rw, vw + far(u) + u * kWave, 0, 0);
             k.w[u] = P == kBF16 ? wv << 16 : wv;
         }
     };
@@ -499,11 +586,11 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // to the tile (a scalar per slot).
     unsigned long long* acc64f = acc64 - lbase;
     uint32_t* acc32f = acc32 - lbase;
-    const int tbase = __builtin_amdgcn_readfirstlane((int)base);
     // A full chunk (every lane holds a posting in every slot) adds without the
     // per-posting predicate; a segment's first (dense) and last chunks are predicated.
-    auto apply = [&](auto dense_form, const Chunk& k) {
-        constexpr bool DENSE = decltype(dense_form)::value;
+    auto apply = [&](auto form, const Chunk& k) {
+        constexpr bool DENSE = decltype(form)::value == 1;
+        constexpr bool PRUNED = decltype(form)::value == 2;
         // slot u's accumulator: the uniform part (block base) goes into the pointer, so each
         // lane adds only its scaled offset
         auto at = [&](auto* acc, int u) {
@@ -512,7 +599,10 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         };
         auto add = [&](auto pred) {
             constexpr bool PRED = decltype(pred)::value;
-            auto ok = [&](int u) { return !PRED || ((u > 0 || lane >= k.lo) && lane + u * kWave < k.n); };
+            auto ok = [&](int u) {
+                return (!PRUNED || !((k.skip >> u) & 1u)) &&
+                       (!PRED || ((u > 0 || lane >= k.lo) && lane + u * kWave < k.n));
+            };
             if constexpr (AF == kAccFx64) {
                 unsigned long long* acc = DENSE ? acc64 : acc64f;
                 const double qd = uniform_f64(sh.seg_qd[k.seg]);
@@ -546,35 +636,73 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     };
     // Chunks c = wave, wave + NW, ... below `end`; returns the wavefront's first chunk at
     // or past `end`.
-    auto run = [&](auto use_tab, auto dense_form, int c, int end) -> int {
+    auto run = [&](auto use_tab, auto form, int c, int end) -> int {
         Chunk A, B;
-        load(use_tab, dense_form, c, A, c < end);
+        load(use_tab, form, c, A, c < end);
         while (c < end) {
             const int cb = c + NW;
-            load(use_tab, dense_form, cb, B, cb < end);
-            apply(dense_form, A);
+            load(use_tab, form, cb, B, cb < end);
+            apply(form, A);
             if (cb >= end) return cb;
             const int ca = cb + NW;
-            load(use_tab, dense_form, ca, A, ca < end);
-            apply(dense_form, B);
+            load(use_tab, form, ca, A, ca < end);
+            apply(form, B);
             c = ca;
         }
         return c;
     };
+    if constexpr (PR) {
+        // The chunk table must leave the last 2 KiB of the histogram area to the group maxima;
+        // otherwise nothing is skipped (t_lo 0), the non-essential blocks are all read.
+        if (prune_item && total > kHistBins * 4 - 2048) {
+            prune_item = false;
+            t_lo = 0;
+        }
+        u_n = sh.wmax[0];
+#pragma unroll
+        for (int w = 1; w < kMaxQueryNnz / kWave; w++) u_n = sh.wmax[w] > u_n ? sh.wmax[w] : u_n;
+    }
     if (total > 0) {
         int n_dense = 0;
 #pragma unroll
         for (int w = 0; w < kMaxQueryNnz / kWave; w++) n_dense += __popcll(sh.dmask[w]);
         const int total_d = __builtin_amdgcn_readfirstlane(sh.seg_cpre[n_dense]);
-        if (tab) {
+        auto two_loops = [&](auto use_tab) {
             int c = wave;
-            if constexpr (DB) c = total_d > 0 ? run(std::true_type(), std::true_type(), wave, total_d) : wave;
-            run(std::true_type(), std::false_type(), c, total);
-        } else {
-            int c = wave;
-            if constexpr (DB) c = total_d > 0 ? run(std::false_type(), std::true_type(), wave, total_d) : wave;
-            run(std::false_type(), std::false_type(), c, total);
-        }
+            if constexpr (DB) {
+                c = total_d > 0 ? run(use_tab, FDense(), wave, total_d) : wave;
+                run(use_tab, FExact(), c, total);
+            } else if constexpr (PR) {
+                // essential terms, then the largest essential sum of every 64-doc group, then
+                // the non-essential terms block by block
+                c = total_d > 0 ? run(use_tab, FExact(), wave, total_d) : wave;
+                if (total_d < total) {  // non-essential terms exist: whole-block segments
+                    __syncthreads();
+                    for (int gi = tid >> 2; gi < TILE / 64; gi += BS / 4) {
+                        unsigned long long m = 0;
+                        for (int j = 0; j < 16; j++) {
+                            const int d = gi * 64 + (tid & 3) * 16 + j;
+                            if (d < tile_n) {
+                                const unsigned long long v =
+                                    AF == kAccFx64 ? acc64[d] : (unsigned long long)acc32[d];
+                                m = v > m ? v : m;
+                            }
+                        }
+                        unsigned long long o = __shfl_xor(m, 1, kWave);
+                        m = o > m ? o : m;
+                        o = __shfl_xor(m, 2, kWave);
+                        m = o > m ? o : m;
+                        if ((tid & 3) == 0 && prune_item) gmax[gi] = m;
+                    }
+                    __syncthreads();
+                    run(use_tab, FPrune(), c, total);
+                }
+            } else {
+                run(use_tab, FExact(), c, total);
+            }
+        };
+        if (tab) two_loops(std::true_type());
+        else two_loops(std::false_type());
     }
     __syncthreads();
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
@@ -601,7 +729,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
 // 512-thread workgroups per CU, which is what their LDS footprint allows.
 // Phases 3 and 4 (the listed queries' rows scored again) use one workgroup per tile
 // walking the list. W: the wide-range form (phase 4).
-template <int P, int TS, int CH, bool W = false>
+template <int P, int TS, int CH, bool W = false, bool PR = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_tiled(
     DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
     int phase, int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand,
@@ -609,9 +737,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ TileShared sh;
     const int64_t tile = phase_tile(phase, stride, (int64_t)blockIdx.x);
-    constexpr bool DB = P != kU8 && !W;
+    constexpr bool DB = P != kU8 && !W && !PR;
     if (phase < 3) {
-        score_tile<P, TS, CH, DB, W>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state, cand);
+        score_tile<P, TS, CH, DB, W, PR>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state,
+                                         cand);
         return;
     }
     // rows of the queries that fell back from fused filtering (phase 3) or were found
@@ -668,6 +797,230 @@ __global__ __launch_bounds__(256) void k_work_order(DevBatch qb, int32_t q0, int
         r += (wj > wi) || (wj == wi && j < i);
     }
     order[r] = i;
+}
+
+// ------------------------------------------------------------- group --
+//
+// Shared traversal with explicit sharing: a work item is (doc tile, group of G
+// queries). The LDS holds G accumulator tiles of 8192 docs (128 KiB: G = 4 with
+// 32-bit sums for bf16 and uint8, G = 2 with 64-bit fixed point for fp32). The
+// segments are those of the union of the group's terms (built on the host, with
+// each member's weight per union term, 0 where the member lacks the term), so a
+// posting chunk is loaded once and scatter-added into the tile of every member
+// that holds its term. The items of a tile run on one XCD (tile-major, as in the
+// persistent kernel), groups in the host's order (heaviest first).
+template <int MT, int G>
+struct GroupShared {
+    union {
+        struct {
+            int64_t beg[MT];
+            int32_t len[MT];
+            int32_t cpre[MT + 1];
+        } seg;
+        uint32_t hist[kHistBins];  // the flush histogram, once the segments are no longer read
+    };
+    uint32_t w[MT][G];  // per union term, each member's w_q (fp32 bits) or uint8 impact
+    uint16_t tab[kGroupChunkTab];  // chunk -> union term, when the item has at most that many chunks
+    int32_t wave_sum[16];
+    int64_t item;
+};
+
+template <int P, int CH>
+__global__ __launch_bounds__(group_size<P>() * kMaxQueryNnz) __attribute__((amdgpu_waves_per_eu(4))) void k_score_group(
+    DevIndex ix, DevBatch qb, uint32_t* __restrict__ counters, uint32_t* __restrict__ S, int64_t ld,
+    uint32_t* __restrict__ hist1, int phase, int stride, SelState* __restrict__ state,
+    unsigned long long* __restrict__ cand) {
+    constexpr int G = group_size<P>();
+    constexpr int MT = G * kMaxQueryNnz;  // most union terms of a group; one thread each
+    constexpr int TS = kGroupTileShift, TILE = 1 << TS, BS = MT, NW = BS / kWave, U = CH / kWave;
+    static_assert(NW <= 16, "wave sums");
+    constexpr bool FX = P != kU8;
+    constexpr int AF = acc_form<P>();
+    constexpr int AW = AF == kAccFx64 ? 2 : 1;  // accumulator words per doc
+    extern __shared__ __align__(16) uint32_t lds[];  // [G][TILE * AW]
+    __shared__ GroupShared<MT, G> sh;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int x = (int)(blockIdx.x & 7);
+    const int64_t n_tiles = phase_tiles(phase, stride, (ix.n_docs + TILE - 1) >> TS);
+    const int64_t tiles_x = n_tiles > x ? (n_tiles - x + 7) / 8 : 0;
+    const int ng = qb.g_count[0];
+    const int64_t items = tiles_x * ng;
+    using WT = std::conditional_t<P == kU8, uint8_t, std::conditional_t<P == kBF16, uint16_t, uint32_t>>;
+    for (;;) {
+        if (tid == 0) sh.item = (int64_t)atomicAdd(&counters[x], 1u);
+        __syncthreads();
+        const int64_t item = sh.item;
+        if (item >= items) break;
+        const int64_t tile = phase_tile(phase, stride, x + 8 * (item / ng));
+        const int g = (int)(item % ng);
+        const int64_t base = tile << TS;
+        const int tile_n = (int)min((int64_t)TILE, ix.n_docs - base);
+        const int lbase = (int)(base & 0xFFFF);
+        const int gr = qb.g_row[g], nu = qb.g_row[g + 1] - gr;
+        for (int i = tid; i < G * TILE * AW; i += BS) lds[i] = 0u;
+        // segments of the union terms in this tile; a term no member weighs adds nothing
+        const int64_t g0 = tile << (TS - kGrainShift);
+        const int64_t g1 = min(g0 + (int64_t)(1 << (TS - kGrainShift)), ix.n_grains);
+        int c = 0;
+        if (tid < nu) {
+            const int term = qb.g_term[gr + tid];
+            const int32_t* row = ix.tile_off + (int64_t)term * (ix.n_grains + 1);
+            const int a = row[g0], b = row[g1];
+            bool any = false;
+#pragma unroll
+            for (int m = 0; m < G; m++) {
+                uint32_t wv;
+                if constexpr (FX) wv = __float_as_uint(qb.g_wq[(int64_t)(gr + tid) * G + m]);
+                else wv = (uint32_t)qb.g_w8[(int64_t)(gr + tid) * G + m];
+                sh.w[tid][m] = wv;
+                any |= wv != 0u;  // weights are >= 0: a zero bit pattern is a zero weight
+            }
+            sh.seg.beg[tid] = ix.term_off[term] + a;
+            sh.seg.len[tid] = any ? b - a : 0;
+            c = any ? (b - a + CH - 1) / CH : 0;
+        }
+        // exclusive prefix of the chunk counts over the union terms (one per thread)
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int v = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += v;
+        }
+        if (lane == kWave - 1) sh.wave_sum[wave] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            const int ws_ = sh.wave_sum[w];
+            before += w < wave ? ws_ : 0;
+            total += ws_;
+        }
+        if (tid < nu) sh.seg.cpre[tid] = before + incl - c;
+        if (tid == 0) sh.seg.cpre[MT] = total;
+        // chunk table: each union term writes its chunks' entries
+        const bool use_tab = total <= kGroupChunkTab;
+        if (use_tab && tid < nu)
+            for (int j = 0; j < c; j++) sh.tab[before + incl - c + j] = (uint16_t)tid;
+        __syncthreads();
+        struct Chunk {
+            uint32_t doc[U];
+            uint32_t w[U];
+            int seg, n;
+        };
+        auto load = [&](int cc, Chunk& k, bool valid) {
+            // segment of chunk cc: the chunk table, else a binary search over the prefix
+            const int want = valid ? cc : 0;
+            int lo = 0;
+            if (use_tab) {
+                lo = total > 0 ? (int)sh.tab[want] : 0;
+            } else {
+                int hi = max(nu - 1, 0);
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sh.seg.cpre[mid] <= want) lo = mid; else hi = mid - 1;
+                }
+            }
+            lo = __builtin_amdgcn_readfirstlane(lo);
+            const int off = __builtin_amdgcn_readfirstlane((want - sh.seg.cpre[lo]) * CH);
+            const int n = valid ? __builtin_amdgcn_readfirstlane(min(CH, sh.seg.len[lo] - off)) : 0;
+            const int64_t pp = sh.seg.beg[lo] + off;
+            const int64_t p0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(pp >> 32)) << 32) |
+                                         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pp));
+            k.seg = lo;
+            k.n = n;
+            const __amdgpu_buffer_rsrc_t rid = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint16_t*>(ix.post_lo + p0), (short)0, n * 2, kRawBufferWord3);
+            const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<WT*>(reinterpret_cast<const WT*>(ix.post_w) + p0), (short)0, n * (int)sizeof(WT),
+                kRawBufferWord3);
+            const int z = (int)((uint64_t)p0 >> 48);  // 0, but not a loop invariant (see score_tile)
+            const int vid = (lane << 1) + z;
+            const int vw = lane * (int)sizeof(WT) + z;
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                k.doc[u] = __builtin_amdgcn_raw_buffer_load_b16(rid, vid + u * kWave * 2, 0, 0);
+                uint32_t wv;
+                if constexpr (sizeof(WT) == 4) wv = __builtin_amdgcn_raw_buffer_load_b32(rw, vw + u * kWave * 4, 0, 0);
+                else if constexpr (sizeof(WT) == 2) wv = __builtin_amdgcn_raw_buffer_load_b16(rw, vw + u * kWave * 2, 0, 0);
+                else wv = __builtin_amdgcn_raw_buffer_load_b8(rw, vw + u * kWave, 0, 0);
+                k.w[u] = P == kBF16 ? wv << 16 : wv;
+            }
+        };
+        // the members' scales 2^F (fixed point): w_q * 2^F is then exact, as q_fx
+        double inv_scale[G];
+#pragma unroll
+        for (int m = 0; m < G; m++) {
+            const int ql = qb.g_member[g * G + m];
+            inv_scale[m] = (FX && ql >= 0) ? 1.0 / qb.q_scale[ql] : 0.0;
+        }
+        // a chunk's postings into the tile of every member holding its term
+        auto apply = [&](const Chunk& k) {
+            auto add = [&](auto pred) {
+                constexpr bool PRED = decltype(pred)::value;
+                auto ok = [&](int u) { return !PRED || lane + u * kWave < k.n; };
+#pragma unroll
+                for (int m = 0; m < G; m++) {
+                    const uint32_t wm = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.w[k.seg][m]);
+                    if (wm == 0u) continue;
+                    if constexpr (AF == kAccFx64) {
+                        const double qd = (double)__uint_as_float(wm) * inv_scale[m];
+                        unsigned long long* acc = reinterpret_cast<unsigned long long*>(lds) + m * TILE - lbase;
+#pragma unroll
+                        for (int u = 0; u < U; u++)
+                            if (ok(u)) atomicAdd(acc + k.doc[u], fx_product(qd, k.w[u]));
+                    } else if constexpr (AF == kAccFx32) {
+                        const double qd = (double)__uint_as_float(wm) * inv_scale[m];
+                        uint32_t* acc = lds + m * TILE - lbase;
+#pragma unroll
+                        for (int u = 0; u < U; u++)
+                            if (ok(u)) atomicAdd(acc + k.doc[u], (uint32_t)fx_product(qd, k.w[u]));
+                    } else {
+                        const uint32_t q8v = wm;
+                        uint32_t* acc = lds + m * TILE - lbase;
+#pragma unroll
+                        for (int u = 0; u < U; u++)
+                            if (ok(u)) atomicAdd(acc + k.doc[u], q8v * k.w[u]);
+                    }
+                }
+            };
+            if (k.n == CH) add(std::false_type());
+            else add(std::true_type());
+        };
+        {
+            int cc = wave;
+            Chunk A, B;
+            load(cc, A, cc < total);
+            while (cc < total) {
+                const int cb = cc + NW;
+                load(cb, B, cb < total);
+                apply(A);
+                if (cb >= total) break;
+                const int ca = cb + NW;
+                load(ca, A, ca < total);
+                apply(B);
+                cc = ca;
+            }
+        }
+        __syncthreads();
+        // flush every member's tile (the histogram reuses the segment area)
+        uint32_t* hist = sh.hist;
+        for (int m = 0; m < G; m++) {
+            const int ql = qb.g_member[g * G + m];
+            if (ql < 0 || qb.k[ql] == 0) continue;  // uniform: read from global memory
+            for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
+            __syncthreads();
+            SelState* st = state + ql;
+            const bool fused_q = phase == 2 && st->fused == 1;
+            const bool app = fused_q && !st->fused_over;
+            const bool write = !fused_q || P == kBF16;
+            const bool count = !(fused_q && P != kBF16);
+            flush_tile<BS, AF>(lds + m * TILE * AW, hist, tile_n, base, S + (int64_t)ql * ld + base,
+                               qb.first_shift[ql], FX ? qb.q_scale[ql] : 1.0, hist1 + (int64_t)ql * kHistBins, app,
+                               app ? st->bound : 0ull, st, cand + (int64_t)ql * kCandCap, write, count);
+            __syncthreads();
+        }
+    }
 }
 
 // ------------------------------------------------------------ atomic --
@@ -840,7 +1193,7 @@ hipError_t by_precision(int p, F f) {
 
 template <int P, int TS, int CH>
 hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, bool persistent,
-                            const Workspace& ws, int64_t ld, hipStream_t s, int phase, int stride) {
+                            const Workspace& ws, int64_t ld, hipStream_t s, int phase, int stride, bool prune) {
     const int64_t n_tiles = phase_tiles(phase, stride, (ix.n_docs + (1 << TS) - 1) >> TS);
     if (n_tiles <= 0) return hipSuccess;
     const size_t lds = (size_t)((1 << TS) * (acc_form<P>() == kAccFx64 ? 2 : 1) + kHistBins) * 4;
@@ -860,6 +1213,24 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         }
     }
     if (!persistent) {
+        // block-max pruning (non-seed tiles): the default tile and chunk of fp32 and uint8 only
+        constexpr bool kPrunable = ((P == kFP32 && TS == 13) || (P == kU8 && TS == 14)) && CH == 1024;
+        if constexpr (kPrunable) {
+            if (prune && phase == 2) {
+                static const hipError_t pattr = hipFuncSetAttribute(
+                    (const void*)k_score_tiled<P, TS, CH, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                    (int)lds);
+                if (pattr != hipSuccess) {
+                    g_failed_launch = "hipFuncSetAttribute(k_score_tiled, pruning)";
+                    return pattr;
+                }
+                hipLaunchKernelGGL((k_score_tiled<P, TS, CH, false, true>), dim3((unsigned)n_tiles, (unsigned)qt),
+                                   dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1, phase, stride, ws.state,
+                                   ws.cand, (const uint32_t*)ws.counters, (const int32_t*)ws.rescore_list);
+                GS_CHECK_LAUNCH("k_score_tiled (pruning)");
+                return hipSuccess;
+            }
+        }
         hipLaunchKernelGGL((k_score_tiled<P, TS, CH>), dim3((unsigned)n_tiles, phase == 3 ? 1u : (unsigned)qt),
                            dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand,
                            (const uint32_t*)ws.counters, (const int32_t*)ws.rescore_list);
@@ -893,13 +1264,13 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
 
 template <int P, int TS>
 hipError_t tiled_chunk(const DevIndex& ix, const DevBatch& qb, int32_t q0, int32_t qt, int chunk, bool persistent,
-                       const Workspace& ws, int64_t ld, hipStream_t s, int phase, int stride) {
+                       const Workspace& ws, int64_t ld, hipStream_t s, int phase, int stride, bool prune) {
     switch (chunk) {
-        case 64: return launch_tiled_one<P, TS, 64>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
-        case 128: return launch_tiled_one<P, TS, 128>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
-        case 256: return launch_tiled_one<P, TS, 256>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
-        case 512: return launch_tiled_one<P, TS, 512>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
-        case 1024: return launch_tiled_one<P, TS, 1024>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride);
+        case 64: return launch_tiled_one<P, TS, 64>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride, prune);
+        case 128: return launch_tiled_one<P, TS, 128>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride, prune);
+        case 256: return launch_tiled_one<P, TS, 256>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride, prune);
+        case 512: return launch_tiled_one<P, TS, 512>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride, prune);
+        case 1024: return launch_tiled_one<P, TS, 1024>(ix, qb, q0, qt, persistent, ws, ld, s, phase, stride, prune);
     }
     return hipErrorInvalidValue;
 }
@@ -932,12 +1303,63 @@ hipError_t launch_score_tiled(const DevIndex& ix, const DevBatch& qb, int32_t q0
         constexpr int P = decltype(pc)::value;
         const bool persistent = o.kernel == 4;  // GS_KERNEL_SHARED: persistent, tile-major, XCD-aware
         switch (o.tile_shift) {
-            case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
-            case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
+            case 13: return tiled_chunk<P, 13>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride, o.prune != 0);
+            case 14: return tiled_chunk<P, 14>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride, o.prune != 0);
             case 15:
                 if constexpr (acc_form<P>() != kAccFx64)
-                    return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride);
+                    return tiled_chunk<P, 15>(ix, qb, q0, qt, o.chunk, persistent, ws, ld, s, phase, stride, o.prune != 0);
                 return hipErrorInvalidValue;  // 32768 64-bit accumulators exceed one CU's LDS
+        }
+        return hipErrorInvalidValue;
+    });
+}
+
+template <int P, int CH>
+hipError_t launch_group_one(const DevIndex& ix, const DevBatch& qb, const Workspace& ws, int64_t ld, hipStream_t s,
+                            int phase, int stride) {
+    constexpr int TS = kGroupTileShift;
+    const int64_t n_tiles = phase_tiles(phase, stride, (ix.n_docs + (1 << TS) - 1) >> TS);
+    if (n_tiles <= 0) return hipSuccess;
+    const size_t lds = (size_t)group_size<P>() * (1 << TS) * (acc_form<P>() == kAccFx64 ? 8 : 4);
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_score_group<P, CH>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) {
+        g_failed_launch = "hipFuncSetAttribute(k_score_group)";
+        return attr;
+    }
+    // resident workgroups (one per CU), a multiple of the 8 XCDs
+    static const int grid = [&] {
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t p{};
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_score_group<P, CH>,
+                                                         group_size<P>() * kMaxQueryNnz, lds) !=
+            hipSuccess)
+            return 0;
+        return std::max(8, (p.multiProcessorCount * std::max(per_cu, 1)) / 8 * 8);
+    }();
+    if (grid <= 0) return hipErrorInvalidConfiguration;
+    if (phase > 1) {  // the seed-tile launch used the counters
+        const hipError_t e = launch_fill(ws.counters, 8, 0u, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_score_group<P, CH>), dim3((unsigned)grid), dim3(group_size<P>() * kMaxQueryNnz), lds, s,
+                       ix, qb, ws.counters,
+                       ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand);
+    GS_CHECK_LAUNCH("k_score_group");
+    return hipSuccess;
+}
+
+hipError_t launch_score_group(const DevIndex& ix, const DevBatch& qb, const ScoreOpts& o, const Workspace& ws,
+                              hipStream_t s, int phase) {
+    const int stride = phase == 0 ? 1 : o.seed_stride;
+    const int64_t ld = score_ld(ix.n_docs);
+    return by_precision(ix.precision, [&](auto pc) -> hipError_t {
+        constexpr int P = decltype(pc)::value;
+        switch (o.chunk) {
+            case 256: return launch_group_one<P, 256>(ix, qb, ws, ld, s, phase, stride);
+            case 512: return launch_group_one<P, 512>(ix, qb, ws, ld, s, phase, stride);
+            case 1024: return launch_group_one<P, 1024>(ix, qb, ws, ld, s, phase, stride);
         }
         return hipErrorInvalidValue;
     });

@@ -367,7 +367,7 @@ int32_t gs_server_create(gs_index index, const gs_server_opts* opts, gs_server* 
     };
     s->arena_rows = n_rows;
     s->arena_bytes = gs::arena_bytes(info.n_docs, n_rows, info.precision);
-    if (hipMalloc(&s->arena, s->arena_bytes) != hipSuccess) {
+    if (gs::dev_malloc(&s->arena, s->arena_bytes) != hipSuccess) {
         s->arena = nullptr;
         return bail(GS_ENOMEM, "device allocation of the workspace arena failed");
     }
@@ -378,14 +378,13 @@ int32_t gs_server_create(gs_index index, const gs_server_opts* opts, gs_server* 
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
             return bail(GS_EHIP, "stream/event creation failed");
-        if (hipMalloc((void**)&sl.counters, 16 * 4) != hipSuccess ||
-            hipMalloc((void**)&sl.d_ids, out_rows * 4) != hipSuccess ||
-            hipMalloc(&sl.d_scores, out_rows * s->score_size) != hipSuccess)
+        if (gs::dev_malloc((void**)&sl.counters, 16 * 4) != hipSuccess ||
+            gs::dev_malloc((void**)&sl.d_ids, out_rows * 4) != hipSuccess ||
+            gs::dev_malloc(&sl.d_scores, out_rows * s->score_size) != hipSuccess)
             return bail(GS_ENOMEM, "device allocation for a slot failed");
-        if (hipHostMalloc((void**)&sl.h_ids, out_rows * 4, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc(&sl.h_scores, out_rows * s->score_size, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&sl.h_diag, (size_t)o.max_batch * gs::kDiagWords * 4, hipHostMallocDefault) !=
-                hipSuccess)
+        if (gs::pinned_malloc((void**)&sl.h_ids, out_rows * 4) != hipSuccess ||
+            gs::pinned_malloc(&sl.h_scores, out_rows * s->score_size) != hipSuccess ||
+            gs::pinned_malloc((void**)&sl.h_diag, (size_t)o.max_batch * gs::kDiagWords * 4) != hipSuccess)
             return bail(GS_ENOMEM, "pinned host allocation for a slot failed");
         rc = gs_batch_reserve(index, o.max_batch, (int64_t)o.max_batch * GS_MAX_QUERY_NNZ, o.k_max, &sl.batch);
         if (rc != GS_OK) return bail(rc, gs_last_error());

@@ -805,7 +805,7 @@ __global__ void k_diag(int32_t q0, int32_t qt, const SelState* __restrict__ stat
     o[3] = st.overflow;
     o[4] = st.rescore;
     o[5] = st.fused == 1 ? 1 : 0;
-    o[6] = 0;
+    o[6] = st.pruned;
     o[7] = 0;
 }
 

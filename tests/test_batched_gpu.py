@@ -44,10 +44,10 @@ def test_autotune_candidates_agree_and_best_is_one_of_them(tune_data, precision)
     ref_ids, ref_sc = ref_ids.cpu().numpy(), ref_sc.cpu().numpy()
     check_batch(precision, docs, qs, ref_ids, ref_sc, ks, what="default")
     best, table, out = idx.autotune(b, ws, reps=1, cache=False, return_outputs=True)
-    names = {gs.GS_KERNEL_TILED: "tiled", gs.GS_KERNEL_SHARED: "shared"}
+    names = {gs.GS_KERNEL_TILED: "tiled", gs.GS_KERNEL_SHARED: "shared", gs.GS_KERNEL_GROUP: "group"}
     cands = [(c["kernel"], c["tile_docs"], c["chunk"]) for c, _ in table]
     expect_tiles = [8192, 16384] + ([] if precision == "fp32" else [32768])
-    assert len(cands) == 2 * len(expect_tiles) * 4 and len(set(cands)) == len(cands)
+    assert len(cands) == 2 * len(expect_tiles) * 4 + 3 and len(set(cands)) == len(cands)
     assert (best.kernel, best.tile_docs, best.chunk) in cands
     assert all(t > 0 for _, t in table)
     # the autotuner's outputs are the best candidate's result
@@ -83,13 +83,14 @@ def uneven():
     return docs, qs, workload.k_mix(qs.n_rows, seed=65)
 
 
-@pytest.mark.parametrize("precision", ["u8", "bf16"])
-def test_uneven_batch_shared_traversal_and_graph(uneven, precision):
+@pytest.mark.parametrize("precision,kernel", [("u8", "shared"), ("bf16", "shared"), ("u8", "group"),
+                                              ("bf16", "group")])
+def test_uneven_batch_shared_traversal_and_graph(uneven, precision, kernel):
     gs, torch = _gs()
     docs, qs, ks = uneven
     assert qs.n_rows == 1024 and np.diff(qs.row_ptr).max() <= 250
     idx = gs.Index.from_rows(docs, precision)
-    opts = gs.make_opts("shared")
+    opts = gs.make_opts(kernel)
     b = idx.batch(qs, ks, k_max=1000)
     ws = idx.workspace(qs.n_rows, opts)
     ids, sc = idx.search(b, ws, opts)

@@ -44,7 +44,7 @@ def _search(gs, torch, idx, qs, k, k_max, kernel, fused, tile_docs=0):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "u8", "bf16"])
-@pytest.mark.parametrize("kernel", ["tiled", "shared"])
+@pytest.mark.parametrize("kernel", ["tiled", "shared", "group"])
 def test_fused_equals_row_scan(data, precision, kernel):
     gs, torch = _gs()
     docs, qs = data
@@ -67,7 +67,7 @@ def test_fused_tiles_and_large_k(data, tile_docs):
     docs, qs = data
     idx = gs.Index.from_rows(docs, "u8")
     k = np.where(np.arange(qs.n_rows) % 2 == 0, 2000, 7).astype(np.int32)
-    for kernel in ("tiled", "shared"):
+    for kernel in ("tiled", "shared") + (("group",) if tile_docs == 8192 else ()):
         a = _search(gs, torch, idx, qs, k, 2000, kernel, True, tile_docs)
         b = _search(gs, torch, idx, qs, k, 2000, kernel, False, tile_docs)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), kernel
@@ -86,7 +86,7 @@ def test_fused_fallback_on_massive_ties(precision):
     docs = random_rows(rng, 300_000, 60, 1, 8, weight_fn=lambda r, n: np.ones(n))
     qs = random_rows(rng, 40, 60, 1, 6, weight_fn=lambda r, n: np.ones(n))
     idx = gs.Index.from_rows(docs, precision)
-    for kernel in ("tiled", "shared"):
+    for kernel in ("tiled", "shared", "group"):
         a = _search(gs, torch, idx, qs, 1000, 1000, kernel, True)
         b = _search(gs, torch, idx, qs, 1000, 1000, kernel, False)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), kernel
@@ -134,7 +134,7 @@ def test_fused_bf16_band_below_the_candidates(n_terms):
     docs = random_rows(rng, 300_000, 200, n_terms[0], n_terms[1], weight_fn=dy)
     qs = random_rows(rng, 40, 200, 3, 12, weight_fn=dy)
     idx = gs.Index.from_rows(docs, "bf16")
-    for kernel in ("tiled", "shared"):
+    for kernel in ("tiled", "shared", "group"):
         a = _search(gs, torch, idx, qs, 1000, 1000, kernel, True)
         b = _search(gs, torch, idx, qs, 1000, 1000, kernel, False)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), kernel

@@ -30,7 +30,7 @@ def data():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "u8", "bf16"])
-@pytest.mark.parametrize("kernel", ["tiled", "shared"])
+@pytest.mark.parametrize("kernel", ["tiled", "shared", "group"])
 def test_graph_replays_match_direct_search(data, precision, kernel):
     gs, torch = _gs()
     docs, q1, q2 = data

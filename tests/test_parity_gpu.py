@@ -19,7 +19,7 @@ from parity_rules import check_batch, check_exact_f64, check_exact_int
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-KERNELS = ["tiled", "atomic", "docpar", "shared"]
+KERNELS = ["tiled", "atomic", "docpar", "shared", "group"]
 
 
 def _gs():
@@ -87,6 +87,8 @@ def test_dyadic_weights_are_exact_across_tiles(precision, tile_docs, chunk):
     else:
         rid, rsc = oracle.topk_f64(docs, qs, 300)
     kernels = ("tiled", "atomic", "shared") if precision == "fp32" else ("tiled", "shared")
+    if tile_docs == 8192 and chunk >= 256:
+        kernels = kernels + ("group",)  # the group kernel: 8192-doc tiles, chunks of 256+
     for kernel in kernels:
         ids, sc, _ = _run(gs, docs, qs, 300, precision, kernel, tile_docs=tile_docs, chunk=chunk)
         for q in range(qs.n_rows):
@@ -206,7 +208,8 @@ def mid():
 
 @pytest.mark.parametrize("precision,kernel", [("fp32", "tiled"), ("fp32", "atomic"), ("fp32", "docpar"),
                                               ("fp32", "shared"), ("u8", "tiled"), ("u8", "shared"),
-                                              ("bf16", "tiled"), ("bf16", "shared")])
+                                              ("bf16", "tiled"), ("bf16", "shared"), ("fp32", "group"),
+                                              ("u8", "group"), ("bf16", "group")])
 def test_mid_scale_top1000(mid, precision, kernel):
     gs = _gs()
     docs, qs = mid
@@ -295,7 +298,7 @@ def test_full_scale_sampled(full, precision):
     docs, qs = full
     idx = gs.Index.from_rows(docs, precision)
     got = {}
-    for kernel in ("tiled", "shared"):
+    for kernel in ("tiled", "shared", "group"):
         opts = gs.make_opts(kernel)
         b = idx.batch(qs, 1000)
         ids, sc = idx.search(b, idx.workspace(qs.n_rows, opts), opts)
@@ -306,6 +309,7 @@ def test_full_scale_sampled(full, precision):
         torch.cuda.empty_cache()
     ids, sc = got["tiled"]
     assert np.array_equal(ids, got["shared"][0]) and np.array_equal(sc, got["shared"][1]), "tiled vs shared"
+    assert np.array_equal(ids, got["group"][0]) and np.array_equal(sc, got["group"][1]), "tiled vs group"
     sample = qs.subset(np.arange(6))
     check_batch(precision, docs, sample, ids[:6], sc[:6], 1000, n_threads=0, what="8.8M " + precision)
     for q in range(0, qs.n_rows, 25):  # every 25th query: returned scores are the exact scores of those docs

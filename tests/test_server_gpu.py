@@ -26,7 +26,7 @@ def data():
     return docs, qs, k
 
 
-@pytest.mark.parametrize("kernel", ["tiled", "shared"])
+@pytest.mark.parametrize("kernel", ["tiled", "shared", "group"])
 @pytest.mark.parametrize("precision", ["u8", "fp32"])
 def test_results_alone_equal_results_in_the_mix(data, precision, kernel):
     gs, _ = _gs()

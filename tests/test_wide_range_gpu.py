@@ -75,7 +75,7 @@ def data():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-@pytest.mark.parametrize("kernel", ["tiled", "shared", "atomic", "docpar"])
+@pytest.mark.parametrize("kernel", ["tiled", "shared", "group", "atomic", "docpar"])
 @pytest.mark.parametrize("fused", [True, False])
 def test_wide_range_weights_meet_the_rules(data, precision, kernel, fused):
     gs, torch = _gs()
@@ -91,7 +91,7 @@ def test_wide_range_weights_meet_the_rules(data, precision, kernel, fused):
     diag = b.diagnostics()
     assert diag[:, 3].max() == 0, "band overflow"
     check_batch(precision, docs, qs, ids.cpu().numpy(), sc.cpu().numpy(), ks, what="%s %s" % (precision, kernel))
-    if kernel in ("tiled", "shared"):
+    if kernel in ("tiled", "shared", "group"):
         # The fixed-point kernels sum the wide-range queries again in fp64. Without fused
         # filtering no other query takes that pass. With it, an fp32 query is checked against
         # the k-th score of the seed tiles (a lower bound): query 4 ({A, B}, k = 300) has fewer

@@ -23,7 +23,7 @@ def _gs():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "u8", "bf16"])
-@pytest.mark.parametrize("kernel", ["tiled", "shared"])
+@pytest.mark.parametrize("kernel", ["tiled", "shared", "group"])
 def test_noalloc_matches_the_workspace_search(precision, kernel):
     gs, torch = _gs()
     docs = workload.collection(150_000, seed=81)
