@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--kernel", default="tiled", choices=["tiled", "atomic", "docpar", "shared", "group"])
     ap.add_argument("--tile-docs", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--forms", default="u8,bf16,fp32:shared,u8:shared,bf16:shared",
+    ap.add_argument("--forms", default="u8,bf16,fp32:shared,u8:shared,bf16:shared,u8:group",
                     help="other precision[:kernel[:chunk[:prune]]] forms to time (comma list, or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16, help="queries timed on the CPU oracle (0 = skip)")
     ap.add_argument("--profile", action="store_true", help="main form only, no CPU leg (for profiler runs)")
@@ -350,7 +350,7 @@ def run_batched(gs, torch, docs, args, indexes):
             status = "exact on %d sampled queries" % s
         except AssertionError as e:
             status = "MISMATCH: " + str(e)[:160]
-        names = {1: "tiled", 4: "shared"}
+        names = {v: k for k, v in gs.KERNELS.items()}
         res[prec] = {"qps_plain": round(nq / (plain_ms / 1e3), 1), "qps_graph": round(nq / (graph_ms / 1e3), 1),
                      "ms_plain": round(plain_ms, 3), "ms_graph": round(graph_ms, 3),
                      "small_batch_16": {"ms_plain": round(small_plain, 3), "ms_graph": round(small_graph, 3)},
