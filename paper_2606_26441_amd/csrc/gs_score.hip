@@ -30,7 +30,8 @@
 // weights, as one byte per posting from the 64-block's first doc. With fused
 // candidate filtering a search runs them in phases: the seed tiles, then the
 // other tiles appending candidates at or above a bound while they flush, then a
-// pass that writes the rows of the queries that fell back (see gs_topk.hip).
+// pass that writes the rows of the queries that fell back (k_score_listed; see
+// gs_topk.hip).
 #include <algorithm>
 #include <type_traits>
 
@@ -727,24 +728,31 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
 // workgroups, so each query streams its own postings from HBM.
 // Both scoring kernels are held to 128 VGPRs (four wavefronts per SIMD): two
 // 512-thread workgroups per CU, which is what their LDS footprint allows.
-// Phases 3 and 4 (the listed queries' rows scored again) use one workgroup per tile
-// walking the list. W: the wide-range form (phase 4).
-template <int P, int TS, int CH, bool W = false, bool PR = false>
+// PR: block-max pruning (phase 2).
+template <int P, int TS, int CH, bool PR = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_tiled(
+    DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
+    int phase, int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    __shared__ TileShared sh;
+    const int64_t tile = phase_tile(phase, stride, (int64_t)blockIdx.x);
+    constexpr bool DB = P != kU8 && !PR;
+    score_tile<P, TS, CH, DB, false, PR>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state, cand);
+}
+
+// The rows of the listed queries scored again, one workgroup per tile walking the list
+// (usually empty): those that fell back from fused filtering (phase 3) or were found wide
+// range (phase 4, W: fp64 accumulation). score_tile skips the other kind. A kernel of its
+// own, so that the per-query kernel's registers hold one copy of the scoring loop.
+template <int P, int TS, int CH, bool W = false>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_score_listed(
     DevIndex ix, DevBatch qb, int32_t q0, uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
     int phase, int stride, SelState* __restrict__ state, unsigned long long* __restrict__ cand,
     const uint32_t* __restrict__ counters, const int32_t* __restrict__ rescore_list) {
     extern __shared__ __align__(16) uint32_t lds[];
     __shared__ TileShared sh;
     const int64_t tile = phase_tile(phase, stride, (int64_t)blockIdx.x);
-    constexpr bool DB = P != kU8 && !W && !PR;
-    if (phase < 3) {
-        score_tile<P, TS, CH, DB, W, PR>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state,
-                                         cand);
-        return;
-    }
-    // rows of the queries that fell back from fused filtering (phase 3) or were found
-    // wide range (phase 4); usually none. score_tile skips the other kind.
+    constexpr bool DB = P != kU8 && !W;
     const int nres = (int)counters[8];
     for (int r = 0; r < nres; r++) {
         score_tile<P, TS, CH, DB, W>(ix, qb, q0, tile, rescore_list[r], S, ld, hist1, lds, sh, phase, state, cand);
@@ -1203,6 +1211,9 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
             hipError_t e = hipFuncSetAttribute((const void*)k_score_tiled<P, TS, CH>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e == hipSuccess)
+                e = hipFuncSetAttribute((const void*)k_score_listed<P, TS, CH>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e == hipSuccess)
                 e = hipFuncSetAttribute((const void*)k_score_persistent<P, TS, CH>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             return e;
@@ -1218,22 +1229,27 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
         if constexpr (kPrunable) {
             if (prune && phase == 2) {
                 static const hipError_t pattr = hipFuncSetAttribute(
-                    (const void*)k_score_tiled<P, TS, CH, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                    (int)lds);
+                    (const void*)k_score_tiled<P, TS, CH, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
                 if (pattr != hipSuccess) {
                     g_failed_launch = "hipFuncSetAttribute(k_score_tiled, pruning)";
                     return pattr;
                 }
-                hipLaunchKernelGGL((k_score_tiled<P, TS, CH, false, true>), dim3((unsigned)n_tiles, (unsigned)qt),
+                hipLaunchKernelGGL((k_score_tiled<P, TS, CH, true>), dim3((unsigned)n_tiles, (unsigned)qt),
                                    dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1, phase, stride, ws.state,
-                                   ws.cand, (const uint32_t*)ws.counters, (const int32_t*)ws.rescore_list);
+                                   ws.cand);
                 GS_CHECK_LAUNCH("k_score_tiled (pruning)");
                 return hipSuccess;
             }
         }
-        hipLaunchKernelGGL((k_score_tiled<P, TS, CH>), dim3((unsigned)n_tiles, phase == 3 ? 1u : (unsigned)qt),
-                           dim3(512), lds, s, ix, qb, q0, ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand,
-                           (const uint32_t*)ws.counters, (const int32_t*)ws.rescore_list);
+        if (phase == 3) {
+            hipLaunchKernelGGL((k_score_listed<P, TS, CH>), dim3((unsigned)n_tiles, 1u), dim3(512), lds, s, ix, qb, q0,
+                               ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand, (const uint32_t*)ws.counters,
+                               (const int32_t*)ws.rescore_list);
+            GS_CHECK_LAUNCH("k_score_listed");
+            return hipSuccess;
+        }
+        hipLaunchKernelGGL((k_score_tiled<P, TS, CH>), dim3((unsigned)n_tiles, (unsigned)qt), dim3(512), lds, s, ix,
+                           qb, q0, ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand);
         GS_CHECK_LAUNCH("k_score_tiled");
         return hipSuccess;
     }
@@ -1374,16 +1390,16 @@ hipError_t launch_score_wide(const DevIndex& ix, const DevBatch& qb, int32_t q0,
     const int64_t ld = score_ld(ix.n_docs);
     auto go = [&](auto pc) -> hipError_t {
         constexpr int P = decltype(pc)::value;
-        static const hipError_t attr = hipFuncSetAttribute((const void*)k_score_tiled<P, TS, CH, true>,
+        static const hipError_t attr = hipFuncSetAttribute((const void*)k_score_listed<P, TS, CH, true>,
                                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (attr != hipSuccess) {
-            g_failed_launch = "hipFuncSetAttribute(k_score_tiled, wide)";
+            g_failed_launch = "hipFuncSetAttribute(k_score_listed, wide)";
             return attr;
         }
-        hipLaunchKernelGGL((k_score_tiled<P, TS, CH, true>), dim3((unsigned)n_tiles, 1u), dim3(512), lds, s, ix, qb,
+        hipLaunchKernelGGL((k_score_listed<P, TS, CH, true>), dim3((unsigned)n_tiles, 1u), dim3(512), lds, s, ix, qb,
                            q0, ws.scores, ld, ws.hist1, 4, 1, ws.state, ws.cand, (const uint32_t*)ws.counters,
                            (const int32_t*)ws.rescore_list);
-        GS_CHECK_LAUNCH("k_score_tiled (wide)");
+        GS_CHECK_LAUNCH("k_score_listed (wide)");
         return hipSuccess;
     };
     if (ix.precision == kFP32) return go(std::integral_constant<int, kFP32>());
