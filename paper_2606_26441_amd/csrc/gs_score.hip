@@ -629,7 +629,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
                 const uint32_t q8v = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.seg_q8[k.seg]);
 #pragma unroll
                 for (int u = 0; u < U; u++)
-                    if (ok(u)) atomicAdd(at(acc, u), q8v * k.w[u]);
+                    if (ok(u)) atomicAdd(at(acc, u), __umul24(q8v, k.w[u]));  // both below 256: full rate
             }
         };
         if (k.n == CH && k.lo == 0) add(std::false_type());
@@ -988,7 +988,7 @@ __global__ __launch_bounds__(group_size<P>() * kMaxQueryNnz) __attribute__((amdg
                         uint32_t* acc = lds + m * TILE - lbase;
 #pragma unroll
                         for (int u = 0; u < U; u++)
-                            if (ok(u)) atomicAdd(acc + k.doc[u], q8v * k.w[u]);
+                            if (ok(u)) atomicAdd(acc + k.doc[u], __umul24(q8v, k.w[u]));
                     }
                 }
             };
