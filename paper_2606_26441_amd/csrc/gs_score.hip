@@ -144,13 +144,18 @@ __device__ __forceinline__ void append_candidates(bool take, unsigned long long 
 }
 
 // write: store the scores in the row; count: add the tile to the first-digit histogram.
-template <int BS, int AF>
+// Q: 0 for a plain tile (doc d in accumulator d); else a tile in quarters (doc d in
+// accumulator (d % 4) * Q + d / 4, Q = tile size / 4), as the four-postings-per-lane loads of
+// score_tile leave it.
+template <int BS, int AF, int Q = 0>
 __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, int tile_n, int64_t base, uint32_t* Sq,
                                            int fs, double scale, uint32_t* hist_out, bool append,
                                            unsigned long long bound, SelState* st, unsigned long long* C,
                                            bool write, bool count) {
     const int tid = threadIdx.x;
     const int n4 = tile_n >> 2;
+    auto at4 = [](int i, int j) { return Q ? j * Q + i : 4 * i + j; };   // doc 4 i + j
+    auto at = [](int d) { return Q ? (d & 3) * Q + (d >> 2) : d; };
     if constexpr (AF == kAccFx64) {
         if (!write && !count) {
             // Only candidates matter (no row, no histogram). A doc whose float score
@@ -165,7 +170,7 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
             for (int i = tid; i < n4; i += BS) {
                 unsigned long long a[4];
 #pragma unroll
-                for (int j = 0; j < 4; j++) a[j] = acc[4 * i + j];
+                for (int j = 0; j < 4; j++) a[j] = acc[at4(i, j)];
                 const unsigned long long m01 = a[0] > a[1] ? a[0] : a[1];
                 const unsigned long long m23 = a[2] > a[3] ? a[2] : a[3];
                 if (!__ballot((m01 > m23 ? m01 : m23) >= t_lo)) continue;
@@ -178,7 +183,7 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
                 }
             }
             for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
-                const uint32_t v = __float_as_uint((float)((double)acc[i] * scale));
+                const uint32_t v = __float_as_uint((float)((double)acc[at(i)] * scale));
                 const unsigned long long c = comp_key(v, (uint32_t)(base + i));
                 append_candidates(c >= bound, c, st, C);
             }
@@ -190,11 +195,19 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
         if constexpr (AF == kAccFx64) {
             const unsigned long long* acc = (const unsigned long long*)acc_v;
 #pragma unroll
-            for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)acc[4 * i + j] * scale));
+            for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)acc[at4(i, j)] * scale));
         } else if constexpr (AF == kAccF64) {
             const double* acc = (const double*)acc_v;
 #pragma unroll
-            for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)acc[4 * i + j]);
+            for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)acc[at4(i, j)]);
+        } else if constexpr (Q != 0) {
+            const uint32_t* acc = (const uint32_t*)acc_v;
+#pragma unroll
+            for (int j = 0; j < 4; j++) v[j] = acc[at4(i, j)];
+            if constexpr (AF == kAccFx32) {
+#pragma unroll
+                for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)v[j] * scale));
+            }
         } else {
             const uint4 u = reinterpret_cast<const uint4*>(acc_v)[i];
             v[0] = u.x; v[1] = u.y; v[2] = u.z; v[3] = u.w;
@@ -221,10 +234,11 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
     }
     for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
         uint32_t v;
-        if constexpr (AF == kAccFx64) v = __float_as_uint((float)((double)((const unsigned long long*)acc_v)[i] * scale));
-        else if constexpr (AF == kAccF64) v = __float_as_uint((float)((const double*)acc_v)[i]);
-        else if constexpr (AF == kAccFx32) v = __float_as_uint((float)((double)((const uint32_t*)acc_v)[i] * scale));
-        else v = ((const uint32_t*)acc_v)[i];
+        const int ai = at(i);
+        if constexpr (AF == kAccFx64) v = __float_as_uint((float)((double)((const unsigned long long*)acc_v)[ai] * scale));
+        else if constexpr (AF == kAccF64) v = __float_as_uint((float)((const double*)acc_v)[ai]);
+        else if constexpr (AF == kAccFx32) v = __float_as_uint((float)((double)((const uint32_t*)acc_v)[ai] * scale));
+        else v = ((const uint32_t*)acc_v)[ai];
         if (write) Sq[i] = v;
         const unsigned long long c = comp_key(v, (uint32_t)(base + i));
         if (count) atomicAdd(&hist[(c >> fs) & (kHistBins - 1)], 1u);
@@ -333,7 +347,15 @@ __device__ __forceinline__ void chunk_at(const TileShared& sh, const uint8_t* ta
 // when every doc it can hold has partial sum + the non-essential bounds' sum below t_lo. A
 // doc of a skipped block can then not reach the bound, so it is no candidate, and every
 // candidate's sum is complete: the result is exact.
-template <int P, int TS, int CH, bool DB, bool W = false, bool PR = false>
+// QD: the 2-byte-id segments are read four postings per lane: one 8-byte load of ids and
+// one load of four weights (4, 8 or 16 bytes) cover a lane's postings 4l .. 4l + 3 of each
+// 256 postings of the chunk, a quarter of the vector memory instructions of one posting per
+// lane and load (those instructions, not HBM or the LDS, bound the shared traversal). Segment
+// starts are rounded down to a multiple of 4 (the postings before the real start are
+// masked). So that the 64 lanes of an add still touch consecutive LDS words where doc ids run
+// consecutively, the tile is kept in quarters: doc x of the tile is accumulator
+// (x % 4) * TILE / 4 + x / 4 (flush_tile reads it back in doc order).
+template <int P, int TS, int CH, bool DB, bool W = false, bool PR = false, bool QD = false>
 __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& qb, int32_t q0, int64_t tile, int ql,
                                            uint32_t* __restrict__ S, int64_t ld, uint32_t* __restrict__ hist1,
                                            uint32_t* lds, TileShared& sh, int phase, SelState* state,
@@ -365,6 +387,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     const int64_t g0 = tile << GPT;
     const int64_t g1 = min(g0 + (int64_t)(1 << GPT), ix.n_grains);
     static_assert(!(PR && DB), "pruning reads 2-byte doc ids");
+    static_assert(!QD || (!DB && !PR && !W && CH % 256 == 0), "quad loads: 2-byte ids, chunks of 256-posting rows");
     static_assert(!PR || (P != kBF16 && !W), "pruning: fp32 and uint8 fixed-point or integer sums");
     // Pruning applies to the non-seed tiles of a query whose seed bound is set; t_lo is the
     // bound's score as a raw sum (no sum below it can give a candidate, see flush_tile).
@@ -435,6 +458,11 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
             zero_weight = q8 == 0u;
         }
         int beg = a, len = b - a, edge = 0;
+        if constexpr (QD) {  // quads: the segment starts at a multiple of 4, edge postings masked
+            beg = a & ~3;
+            len = b - beg;
+            edge = a - beg;
+        }
         if (PR ? (!dense && b > a) : dense) {  // whole blocks: lists start 64-aligned and are padded to 64
             beg = a & ~(kBlock - 1);
             const int end = (b + kBlock - 1) & ~(kBlock - 1);
@@ -519,6 +547,41 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         int n = 0, off = 0;
         chunk_at<decltype(use_tab)::value>(sh, tab, nq, valid ? c : 0, CH, &k.seg, &p0, &n, &off);
         k.skip = 0u;
+        if constexpr (QD && !DENSE && !PRUNED) {
+            // p0 is a multiple of 4: ids as 8-byte loads, weights as 4-, 8- or 16-byte loads, both
+            // covering whole quads (up to 3 postings past the segment, inside the padded list)
+            k.lo = off == 0 ? __builtin_amdgcn_readfirstlane((int)sh.seg_edge[k.seg]) : 0;
+            k.n = valid ? n : 0;
+            const int nrec = valid ? (n + 3) & ~3 : 0;
+            const __amdgpu_buffer_rsrc_t rid = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint16_t*>(ix.post_lo + p0), (short)0, nrec * 2, kRawBufferWord3);
+            const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<WT*>(reinterpret_cast<const WT*>(ix.post_w) + p0), (short)0, nrec * (int)sizeof(WT),
+                kRawBufferWord3);
+            const int z = (int)((uint64_t)p0 >> 48);  // 0, keeps one lane offset per chunk (as below)
+            const int vid = lane * 8 + z;
+            const int vw = lane * 4 * (int)sizeof(WT) + z;
+#pragma unroll
+            for (int q = 0; q < CH / 256; q++) {
+                const auto d = __builtin_amdgcn_raw_buffer_load_b64(rid, vid + q * 512, 0, 0);
+                k.doc[2 * q] = d[0];
+                k.doc[2 * q + 1] = d[1];
+                if constexpr (sizeof(WT) == 1) {
+                    k.w[q] = __builtin_amdgcn_raw_buffer_load_b32(rw, vw + q * 256, 0, 0);
+                } else if constexpr (sizeof(WT) == 2) {
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b64(rw, vw + q * 512, 0, 0);
+                    k.w[2 * q] = w[0];
+                    k.w[2 * q + 1] = w[1];
+                } else {
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rw, vw + q * 1024, 0, 0);
+                    k.w[4 * q] = w[0];
+                    k.w[4 * q + 1] = w[1];
+                    k.w[4 * q + 2] = w[2];
+                    k.w[4 * q + 3] = w[3];
+                }
+            }
+            return;
+        }
         if constexpr (DENSE || PRUNED) {
             const int edge = __builtin_amdgcn_readfirstlane((int)sh.seg_edge[k.seg]);
             const int real_end = sh.seg_len[k.seg] - (edge >> 8) - off;
@@ -600,6 +663,55 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         };
         auto add = [&](auto pred) {
             constexpr bool PRED = decltype(pred)::value;
+            if constexpr (QD && !DENSE && !PRUNED) {
+                // posting q * 256 + 4 lane + j of the chunk; its quarter-tile accumulator, relative
+                // to acc - lbase / 4 (lbase is a multiple of 4, so d16 % 4 is the tile doc's)
+                auto okq = [&](int q, int j) {
+                    const int idx = q * 256 + lane * 4 + j;
+                    return !PRED || (idx >= k.lo && idx < k.n);
+                };
+                auto slot = [&](int q, int j) -> uint32_t {
+                    const uint32_t dw = k.doc[2 * q + (j >> 1)];
+                    const uint32_t d16 = (j & 1) ? (dw >> 16) : (dw & 0xffffu);
+                    return ((d16 & 3u) << (TS - 2)) + (d16 >> 2);
+                };
+                auto wbits = [&](int q, int j) -> uint32_t {  // stored weight (fp32 bits or uint8)
+                    if constexpr (sizeof(WT) == 1) {
+                        return (k.w[q] >> (8 * j)) & 0xffu;
+                    } else if constexpr (sizeof(WT) == 2) {
+                        const uint32_t h = k.w[2 * q + (j >> 1)];
+                        return ((j & 1) ? (h >> 16) : (h & 0xffffu)) << 16;
+                    } else {
+                        return k.w[4 * q + j];
+                    }
+                };
+                if constexpr (AF == kAccFx64) {
+                    unsigned long long* acc = acc64 - (lbase >> 2);
+                    const double qd = uniform_f64(sh.seg_qd[k.seg]);
+#pragma unroll
+                    for (int q = 0; q < CH / 256; q++)
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            if (okq(q, j)) atomicAdd(acc + slot(q, j), fx_product(qd, wbits(q, j)));
+                } else if constexpr (AF == kAccFx32) {
+                    uint32_t* acc = acc32 - (lbase >> 2);
+                    const double qd = uniform_f64(sh.seg_qd[k.seg]);
+#pragma unroll
+                    for (int q = 0; q < CH / 256; q++)
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            if (okq(q, j)) atomicAdd(acc + slot(q, j), (uint32_t)fx_product(qd, wbits(q, j)));
+                } else if constexpr (AF == kAccInt) {
+                    uint32_t* acc = acc32 - (lbase >> 2);
+                    const uint32_t q8v = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.seg_q8[k.seg]);
+#pragma unroll
+                    for (int q = 0; q < CH / 256; q++)
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+                            if (okq(q, j)) atomicAdd(acc + slot(q, j), __umul24(q8v, wbits(q, j)));
+                }
+                return;
+            }
             auto ok = [&](int u) {
                 return (!PRUNED || !((k.skip >> u) & 1u)) &&
                        (!PRED || ((u > 0 || lane >= k.lo) && lane + u * kWave < k.n));
@@ -719,7 +831,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // only: its selection needs no more, and if it falls back, phase 3 scores these tiles
     // again and counts them then (bf16 has no phase 3 and counts here).
     const bool count = !(fused_q && P != kBF16);
-    flush_tile<BS, AF>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
+    flush_tile<BS, AF, (QD ? TILE / 4 : 0)>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
                        (FX && !W) ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins, app, app ? st->bound : 0ull, st,
                        cand + (int64_t)ql * kCandCap, write, count);
 }
@@ -737,7 +849,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ TileShared sh;
     const int64_t tile = phase_tile(phase, stride, (int64_t)blockIdx.x);
     constexpr bool DB = P != kU8 && !PR;
-    score_tile<P, TS, CH, DB, false, PR>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state, cand);
+    constexpr bool QD = !DB && !PR && CH % 256 == 0;  // uint8 weights: four postings per lane and load
+    score_tile<P, TS, CH, DB, false, PR, QD>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state,
+                                             cand);
 }
 
 // The rows of the listed queries scored again, one workgroup per tile walking the list
@@ -788,7 +902,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (item >= items) break;
         const int64_t tile = phase_tile(phase, stride, x + 8 * (item / nq));
         const int ql = phase == 3 ? rescore_list[item % nq] : order[item % nq];
-        score_tile<P, TS, CH, false>(ix, qb, q0, tile, ql, S, ld, hist1, lds, sh, phase, state, cand);
+        // uint8 weights: four postings per lane and load (measured +10 %; the fixed-point forms,
+        // with more arithmetic per posting, ran 4-6 % slower that way)
+        score_tile<P, TS, CH, false, false, false, (P == kU8 && CH % 256 == 0)>(ix, qb, q0, tile, ql, S, ld, hist1,
+                                                                                lds, sh, phase, state, cand);
         __syncthreads();
     }
 }
