@@ -387,7 +387,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     const int64_t g0 = tile << GPT;
     const int64_t g1 = min(g0 + (int64_t)(1 << GPT), ix.n_grains);
     static_assert(!(PR && DB), "pruning reads 2-byte doc ids");
-    static_assert(!QD || (!DB && !PR && !W && CH % 256 == 0), "quad loads: 2-byte ids, chunks of 256-posting rows");
+    static_assert(!QD || (!PR && !W && CH % 256 == 0), "quad loads: chunks of 256-posting rows");
     static_assert(!PR || (P != kBF16 && !W), "pruning: fp32 and uint8 fixed-point or integer sums");
     // Pruning applies to the non-seed tiles of a query whose seed bound is set; t_lo is the
     // bound's score as a raw sum (no sum below it can give a candidate, see flush_tile).
@@ -521,6 +521,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         int32_t blk;      // (dense) lane u < U: first doc of the chunk's block u
         int seg, n, lo;   // postings [lo, n) of the chunk are the segment's (lo > 0: first slot only)
         uint32_t skip;    // (pruned blocks) bit u: block u of the chunk is skipped
+        int32_t bq[CH >= 256 ? CH / 256 : 1];  // (quad loads, dense) the block base of the lane's quad q
     };
     // Chunk forms: 0 exact segment, 2-byte ids; 1 dense term, whole blocks, 1-byte ids;
     // 2 non-essential term under pruning, whole blocks, 2-byte ids, skipped blocks not read.
@@ -547,6 +548,46 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         int n = 0, off = 0;
         chunk_at<decltype(use_tab)::value>(sh, tab, nq, valid ? c : 0, CH, &k.seg, &p0, &n, &off);
         k.skip = 0u;
+        if constexpr (QD && DENSE) {
+            // whole 64-posting blocks (p0 and n multiples of 64): four 1-byte ids per lane and load,
+            // the block base of each of the lane's quads (block 4 q + lane / 16 of the chunk), and
+            // the weights as for the 2-byte form below
+            const int edge = __builtin_amdgcn_readfirstlane((int)sh.seg_edge[k.seg]);
+            const int real_end = sh.seg_len[k.seg] - (edge >> 8) - off;
+            k.lo = off == 0 ? (edge & 0xFF) : 0;
+            k.n = valid ? min(n, real_end) : 0;
+            const int nrec = valid ? n : 0;
+            const __amdgpu_buffer_rsrc_t rid = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint8_t*>(ix.post_b8 + p0), (short)0, nrec, kRawBufferWord3);
+            const __amdgpu_buffer_rsrc_t rbk = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<int32_t*>(ix.blk_first + (p0 >> 6)), (short)0, (nrec >> 6) * 4, kRawBufferWord3);
+            const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<WT*>(reinterpret_cast<const WT*>(ix.post_w) + p0), (short)0, nrec * (int)sizeof(WT),
+                kRawBufferWord3);
+            const int z = (int)((uint64_t)p0 >> 48);  // 0, keeps one lane offset per chunk
+            const int vid = lane * 4 + z;
+            const int vbk = (lane >> 4) * 4 + z;
+            const int vw = lane * 4 * (int)sizeof(WT) + z;
+#pragma unroll
+            for (int q = 0; q < CH / 256; q++) {
+                k.doc[q] = __builtin_amdgcn_raw_buffer_load_b32(rid, vid + q * 256, 0, 0);
+                k.bq[q] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rbk, vbk + q * 16, 0, 0);
+                if constexpr (sizeof(WT) == 1) {
+                    k.w[q] = __builtin_amdgcn_raw_buffer_load_b32(rw, vw + q * 256, 0, 0);
+                } else if constexpr (sizeof(WT) == 2) {
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b64(rw, vw + q * 512, 0, 0);
+                    k.w[2 * q] = w[0];
+                    k.w[2 * q + 1] = w[1];
+                } else {
+                    const auto w = __builtin_amdgcn_raw_buffer_load_b128(rw, vw + q * 1024, 0, 0);
+                    k.w[4 * q] = w[0];
+                    k.w[4 * q + 1] = w[1];
+                    k.w[4 * q + 2] = w[2];
+                    k.w[4 * q + 3] = w[3];
+                }
+            }
+            return;
+        }
         if constexpr (QD && !DENSE && !PRUNED) {
             // p0 is a multiple of 4: ids as 8-byte loads, weights as 4-, 8- or 16-byte loads, both
             // covering whole quads (up to 3 postings past the segment, inside the padded list)
@@ -663,17 +704,23 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         };
         auto add = [&](auto pred) {
             constexpr bool PRED = decltype(pred)::value;
-            if constexpr (QD && !DENSE && !PRUNED) {
-                // posting q * 256 + 4 lane + j of the chunk; its quarter-tile accumulator, relative
-                // to acc - lbase / 4 (lbase is a multiple of 4, so d16 % 4 is the tile doc's)
+            if constexpr (QD && !PRUNED) {
+                // posting q * 256 + 4 lane + j of the chunk; its quarter-tile accumulator. 2-byte
+                // ids: relative to acc - lbase / 4 (lbase is a multiple of 4, so d16 % 4 is the tile
+                // doc's). 1-byte ids (dense): the quad's block base minus the tile base, plus the id.
                 auto okq = [&](int q, int j) {
                     const int idx = q * 256 + lane * 4 + j;
                     return !PRED || (idx >= k.lo && idx < k.n);
                 };
                 auto slot = [&](int q, int j) -> uint32_t {
-                    const uint32_t dw = k.doc[2 * q + (j >> 1)];
-                    const uint32_t d16 = (j & 1) ? (dw >> 16) : (dw & 0xffffu);
-                    return ((d16 & 3u) << (TS - 2)) + (d16 >> 2);
+                    if constexpr (DENSE) {
+                        const uint32_t x = (uint32_t)(k.bq[q] - tbase) + ((k.doc[q] >> (8 * j)) & 0xffu);
+                        return ((x & 3u) << (TS - 2)) + (x >> 2);
+                    } else {
+                        const uint32_t dw = k.doc[2 * q + (j >> 1)];
+                        const uint32_t d16 = (j & 1) ? (dw >> 16) : (dw & 0xffffu);
+                        return ((d16 & 3u) << (TS - 2)) + (d16 >> 2);
+                    }
                 };
                 auto wbits = [&](int q, int j) -> uint32_t {  // stored weight (fp32 bits or uint8)
                     if constexpr (sizeof(WT) == 1) {
@@ -686,7 +733,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
                     }
                 };
                 if constexpr (AF == kAccFx64) {
-                    unsigned long long* acc = acc64 - (lbase >> 2);
+                    unsigned long long* acc = DENSE ? acc64 : acc64 - (lbase >> 2);
                     const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
                     for (int q = 0; q < CH / 256; q++)
@@ -694,7 +741,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
                         for (int j = 0; j < 4; j++)
                             if (okq(q, j)) atomicAdd(acc + slot(q, j), fx_product(qd, wbits(q, j)));
                 } else if constexpr (AF == kAccFx32) {
-                    uint32_t* acc = acc32 - (lbase >> 2);
+                    uint32_t* acc = DENSE ? acc32 : acc32 - (lbase >> 2);
                     const double qd = uniform_f64(sh.seg_qd[k.seg]);
 #pragma unroll
                     for (int q = 0; q < CH / 256; q++)
@@ -702,7 +749,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
                         for (int j = 0; j < 4; j++)
                             if (okq(q, j)) atomicAdd(acc + slot(q, j), (uint32_t)fx_product(qd, wbits(q, j)));
                 } else if constexpr (AF == kAccInt) {
-                    uint32_t* acc = acc32 - (lbase >> 2);
+                    uint32_t* acc = DENSE ? acc32 : acc32 - (lbase >> 2);
                     const uint32_t q8v = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.seg_q8[k.seg]);
 #pragma unroll
                     for (int q = 0; q < CH / 256; q++)
@@ -849,7 +896,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ TileShared sh;
     const int64_t tile = phase_tile(phase, stride, (int64_t)blockIdx.x);
     constexpr bool DB = P != kU8 && !PR;
-    constexpr bool QD = !DB && !PR && CH % 256 == 0;  // uint8 weights: four postings per lane and load
+    // four postings per lane and load: uint8 +5 %, bf16 +4 %; fp32 (16-byte weight loads, the
+    // HBM-bound form) measured 0.7 % slower and keeps one posting per lane
+    constexpr bool QD = !PR && CH % 256 == 0 && P != kFP32;
     score_tile<P, TS, CH, DB, false, PR, QD>(ix, qb, q0, tile, (int)blockIdx.y, S, ld, hist1, lds, sh, phase, state,
                                              cand);
 }
