@@ -167,19 +167,30 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
             const double sb = (double)__uint_as_float((uint32_t)(bound >> 32));
             const unsigned long long t_lo = (unsigned long long)fmax(0.0, floor(sb * (1.0 - 0x1p-22) / scale));
             const unsigned long long* acc = (const unsigned long long*)acc_v;
-            for (int i = tid; i < n4; i += BS) {
-                unsigned long long a[4];
+            // two rounds of reads issued before the first test: one LDS round trip (which the
+            // other workgroup's atomics make long) per two
+            constexpr int R = 2;
+            for (int i0 = tid; i0 < n4; i0 += R * BS) {
+                unsigned long long a[R][4];
 #pragma unroll
-                for (int j = 0; j < 4; j++) a[j] = acc[at4(i, j)];
-                const unsigned long long m01 = a[0] > a[1] ? a[0] : a[1];
-                const unsigned long long m23 = a[2] > a[3] ? a[2] : a[3];
-                if (!__ballot((m01 > m23 ? m01 : m23) >= t_lo)) continue;
-                const uint32_t d0 = (uint32_t)(base + 4 * i);
+                for (int h = 0; h < R; h++) {
+                    const int i = i0 + h * BS;
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const uint32_t v = __float_as_uint((float)((double)a[j] * scale));
-                    const unsigned long long c = comp_key(v, d0 + j);
-                    append_candidates(c >= bound, c, st, C);
+                    for (int j = 0; j < 4; j++) a[h][j] = i < n4 ? acc[at4(i, j)] : 0ull;
+                }
+#pragma unroll
+                for (int h = 0; h < R; h++) {
+                    const int i = i0 + h * BS;
+                    const unsigned long long m01 = a[h][0] > a[h][1] ? a[h][0] : a[h][1];
+                    const unsigned long long m23 = a[h][2] > a[h][3] ? a[h][2] : a[h][3];
+                    if (!__ballot(i < n4 && (m01 > m23 ? m01 : m23) >= t_lo)) continue;
+                    const uint32_t d0 = (uint32_t)(base + 4 * i);
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const uint32_t v = __float_as_uint((float)((double)a[h][j] * scale));
+                        const unsigned long long c = comp_key(v, d0 + j);
+                        append_candidates(i < n4 && c >= bound, c, st, C);
+                    }
                 }
             }
             for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
@@ -190,7 +201,63 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
             return;
         }
     }
-    for (int i = tid; i < n4; i += BS) {
+    // docs 4 i .. 4 i + 3 with their scores v: row store, histogram, candidates
+    auto emit = [&](int i, const uint32_t* v) {
+        if (write) reinterpret_cast<uint4*>(Sq)[i] = make_uint4(v[0], v[1], v[2], v[3]);
+        const uint32_t d0 = (uint32_t)(base + 4 * i);
+        if (count) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) atomicAdd(&hist[(comp_key(v[j], d0 + j) >> fs) & (kHistBins - 1)], 1u);
+        }
+        // a composite reaches the bound only if its score bits reach the bound's: one test
+        // of the lane's largest score first, the exact per-document test only then
+        if (append && __ballot(max(max(v[0], v[1]), max(v[2], v[3])) >= (uint32_t)(bound >> 32))) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const unsigned long long c = comp_key(v[j], d0 + j);
+                append_candidates(c >= bound, c, st, C);
+            }
+        }
+    };
+    int i_first = 0;
+    if constexpr (Q != 0 && (AF == kAccInt || AF == kAccFx32)) {
+        // a tile in quarters: 16 docs 16 g .. 16 g + 15 per lane, one 16-byte read from each
+        // quarter (word 4 g + m of quarter j is doc 16 g + 4 m + j)
+        // (two rounds of reads issued before the first test)
+        const uint32_t* acc = (const uint32_t*)acc_v;
+        const int n16 = tile_n >> 4;
+        constexpr int IT = 2;
+        for (int g0 = tid; g0 < n16; g0 += IT * BS) {
+            uint4 r[IT][4];
+#pragma unroll
+            for (int it = 0; it < IT; it++) {
+                const int g = g0 + it * BS;
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    r[it][j] = g < n16 ? *reinterpret_cast<const uint4*>(acc + j * Q + 4 * g)
+                                       : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int it = 0; it < IT; it++) {
+                const int g = g0 + it * BS;
+                if (g >= n16) break;
+#pragma unroll
+                for (int m = 0; m < 4; m++) {
+                    uint32_t v[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        v[j] = m == 0 ? r[it][j].x : m == 1 ? r[it][j].y : m == 2 ? r[it][j].z : r[it][j].w;
+                    if constexpr (AF == kAccFx32) {
+#pragma unroll
+                        for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)v[j] * scale));
+                    }
+                    emit(4 * g + m, v);
+                }
+            }
+        }
+        i_first = n16 * 4;
+    }
+    for (int i = i_first + tid; i < n4; i += BS) {
         uint32_t v[4];
         if constexpr (AF == kAccFx64) {
             const unsigned long long* acc = (const unsigned long long*)acc_v;
@@ -216,21 +283,7 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
                 for (int j = 0; j < 4; j++) v[j] = __float_as_uint((float)((double)v[j] * scale));
             }
         }
-        if (write) reinterpret_cast<uint4*>(Sq)[i] = make_uint4(v[0], v[1], v[2], v[3]);
-        const uint32_t d0 = (uint32_t)(base + 4 * i);
-        if (count) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) atomicAdd(&hist[(comp_key(v[j], d0 + j) >> fs) & (kHistBins - 1)], 1u);
-        }
-        // a composite reaches the bound only if its score bits reach the bound's: one test
-        // of the lane's largest score first, the exact per-document test only then
-        if (append && __ballot(max(max(v[0], v[1]), max(v[2], v[3])) >= (uint32_t)(bound >> 32))) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const unsigned long long c = comp_key(v[j], d0 + j);
-                append_candidates(c >= bound, c, st, C);
-            }
-        }
+        emit(i, v);
     }
     for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
         uint32_t v;
@@ -300,6 +353,10 @@ struct TileShared {
     uint16_t seg_edge[kMaxQueryNnz];
     unsigned long long dmask[kMaxQueryNnz / kWave];  // dense terms per wavefront of the setup
     unsigned long long wmax[kMaxQueryNnz / kWave];   // pruning: largest bound sum per wavefront
+    // what the flush needs of the query (its selection state and histogram scaling)
+    unsigned long long fl_bound;
+    double fl_scale;
+    int fl_fused, fl_over, fl_shift;
 };
 static_assert(kMaxQueryNnz <= 512 && kMaxQueryNnz % kWave == 0, "segment setup: one thread per query term");
 
@@ -374,13 +431,28 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     if (qb.k[q] == 0) return;  // nothing is selected for it (also every padding slot of a batch)
     if (phase == 3 && state[ql].rescore != 1) return;  // only the queries that fell back
     if (phase == 4 && state[ql].rescore != 2) return;  // only the wide-range queries
+    // What the flush needs of the query: one thread loads it now, so that the latency passes
+    // under the setup, and leaves it in LDS (registers are what the accumulation runs short
+    // of). The state is set before this launch; the cap flag may be set during it by other
+    // workgroups, and a stale 0 only costs appends that the cap check drops.
+    int fl_fused = 0, fl_over = 0, fl_shift = 0;
+    unsigned long long fl_bound = 0;
+    double fl_scale = 1.0;
+    if (threadIdx.x == BS - 1) {
+        const SelState* stq0 = state + ql;
+        fl_fused = stq0->fused;
+        fl_over = stq0->fused_over;
+        fl_bound = stq0->bound;
+        fl_shift = qb.first_shift[q];
+        fl_scale = (FX && !W) ? qb.q_scale[q] : 1.0;
+    }
     const int64_t N = ix.n_docs;
     const int64_t base = tile << TS;
     const int tile_n = (int)min((int64_t)TILE, N - base);
     static_assert(TS <= 16, "a doc tile must lie inside one 65536-doc range");
     const int lbase = (int)(base & 0xFFFF);  // the tile's offset inside its 65536-doc range
 
-    for (int i = tid; i < TILE * AW; i += BS) lds[i] = 0u;
+    for (int i = tid; i < TILE * AW / 4; i += BS) reinterpret_cast<uint4*>(lds)[i] = make_uint4(0u, 0u, 0u, 0u);
 
     const int64_t qa = qb.q_row_ptr[q];
     const int nq = (int)(qb.q_row_ptr[q + 1] - qa);
@@ -473,6 +545,13 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         sh.seg_len[slot] = zero_weight ? 0 : len;  // a zero query weight adds nothing
         sh.seg_edge[slot] = (uint16_t)edge;
     }
+    if (tid == BS - 1) {
+        sh.fl_fused = fl_fused;
+        sh.fl_over = fl_over;
+        sh.fl_bound = fl_bound;
+        sh.fl_shift = fl_shift;
+        sh.fl_scale = fl_scale;
+    }
     __syncthreads();
     if (wave == 0) {
         int c[4];
@@ -483,19 +562,28 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
             c[u] = t < nq ? (sh.seg_len[t] + CH - 1) / CH : 0;
             s += c[u];
         }
-        int incl = s;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int v = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += v;
+        // Exclusive prefix of s over the lanes, one bit plane at a time: a ballot of bit b
+        // and the count of the lower lanes that hold it (no cross-lane traffic through the
+        // LDS, whose queue the other workgroup's atomics keep long).
+        int run = 0, total = 0;
+        for (int b = 0; __ballot((s >> b) != 0) != 0ull; b++) {
+            const unsigned long long m = __ballot((s >> b) & 1);
+            run += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << b;
+            total += __popcll(m) << b;
         }
-        int run = incl - s;
+        // Chunk table: during accumulation the histogram's LDS holds the segment index
+        // of every chunk (one byte each), so a wavefront finds its chunk's segment with
+        // one LDS read; tiles with more chunks than it holds fall back to a search. The
+        // lane that owns a segment writes its entries here, with the prefix at hand.
+        uint8_t* t8 = reinterpret_cast<uint8_t*>(hist);
+        const bool table = total <= kHistBins * 4;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             sh.seg_cpre[lane * 4 + u] = run;
+            if (table)
+                for (int j = 0; j < c[u]; j++) t8[run + j] = (uint8_t)(lane * 4 + u);
             run += c[u];
         }
-        const int total = __shfl(incl, kWave - 1, kWave);
         if (lane == 0) sh.seg_cpre[kMaxQueryNnz] = total;
     }
     __syncthreads();
@@ -503,18 +591,8 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // Chunks go round-robin to the wavefronts. Each wavefront keeps two chunks in
     // flight: the loads of its next chunk are issued before the LDS adds of the
     // current one (two register sets, alternating).
-    // Chunk table: during accumulation the histogram's LDS holds the segment index
-    // of every chunk (one byte each), so a wavefront finds its chunk's segment with
-    // one LDS read; tiles with more chunks than it holds fall back to a search.
     const int total = sh.seg_cpre[nq];
-    const uint8_t* tab = nullptr;
-    if (total <= kHistBins * 4) {
-        uint8_t* t8 = reinterpret_cast<uint8_t*>(hist);
-        for (int sgi = 0; sgi < nq; sgi++)
-            for (int c = sh.seg_cpre[sgi] + tid; c < sh.seg_cpre[sgi + 1]; c += BS) t8[c] = (uint8_t)sgi;
-        tab = t8;
-        __syncthreads();
-    }
+    const uint8_t* tab = total <= kHistBins * 4 ? reinterpret_cast<const uint8_t*>(hist) : nullptr;
     struct Chunk {
         uint32_t doc[U];  // doc id modulo 65536, or (dense) distance to the block's first doc
         uint32_t w[U];    // stored weight as fp32 bits, or the uint8 impact
@@ -871,15 +949,15 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // flushing, no appends once past the cap, and no score row for fp32 and uint8 (bf16 keeps
     // them for its band check). A query that falls back gets its rows from phase 3.
     SelState* st = state + ql;
-    const bool fused_q = phase == 2 && st->fused == 1;
-    const bool app = fused_q && !st->fused_over;
+    const bool fused_q = phase == 2 && sh.fl_fused == 1;
+    const bool app = fused_q && !sh.fl_over;
     const bool write = !fused_q || P == kBF16;
     // The first-digit histogram of a fused fp32/uint8 query keeps the seed tiles' counts
     // only: its selection needs no more, and if it falls back, phase 3 scores these tiles
     // again and counts them then (bf16 has no phase 3 and counts here).
     const bool count = !(fused_q && P != kBF16);
-    flush_tile<BS, AF, (QD ? TILE / 4 : 0)>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, qb.first_shift[q],
-                       (FX && !W) ? qb.q_scale[q] : 1.0, hist1 + (int64_t)ql * kHistBins, app, app ? st->bound : 0ull, st,
+    flush_tile<BS, AF, (QD ? TILE / 4 : 0)>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, sh.fl_shift,
+                       sh.fl_scale, hist1 + (int64_t)ql * kHistBins, app, app ? sh.fl_bound : 0ull, st,
                        cand + (int64_t)ql * kCandCap, write, count);
 }
 
