@@ -147,12 +147,49 @@ __device__ __forceinline__ void append_candidates(bool take, unsigned long long 
 // Q: 0 for a plain tile (doc d in accumulator d); else a tile in quarters (doc d in
 // accumulator (d % 4) * Q + d / 4, Q = tile size / 4), as the four-postings-per-lane loads of
 // score_tile leave it.
+// stg (optional): two LDS words, a stage count (0 on entry) and a base, and an LDS stage of
+// stage_cap entries. With it, a flush that appends stages its candidates and takes one range
+// of the query's buffer for all of them at the end (one global atomic per tile instead of one
+// per wavefront and hit, whose round trips otherwise hold up the tile's last wavefront);
+// candidates past the stage go to the buffer directly.
 template <int BS, int AF, int Q = 0>
 __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, int tile_n, int64_t base, uint32_t* Sq,
                                            int fs, double scale, uint32_t* hist_out, bool append,
                                            unsigned long long bound, SelState* st, unsigned long long* C,
-                                           bool write, bool count) {
+                                           bool write, bool count, int* stg = nullptr,
+                                           unsigned long long* stage = nullptr, int stage_cap = 0) {
     const int tid = threadIdx.x;
+    const bool staged = stg != nullptr && append;
+    auto put = [&](bool take, unsigned long long c) {
+        if (!staged) {
+            append_candidates(take, c, st, C);
+            return;
+        }
+        const unsigned long long m = __ballot(take);
+        if (m == 0) return;
+        const int lane = tid & (kWave - 1);
+        const int leader = __ffsll((long long)__ballot(1)) - 1;
+        int slot = 0;
+        if (lane == leader) slot = atomicAdd(&stg[0], __popcll(m));
+        slot = __shfl(slot, leader, kWave) + __popcll(m & ((1ull << lane) - 1ull));
+        if (take && slot < stage_cap) stage[slot] = c;
+        append_candidates(take && slot >= stage_cap, c, st, C);  // past the stage: to the buffer directly
+    };
+    auto drain = [&]() {
+        if (!staged) return;
+        __syncthreads();
+        const int n = min(stg[0], stage_cap);
+        if (n == 0) return;
+        if (tid == 0) {
+            const int b = atomicAdd(&st->n_cand, n);
+            if (b + n > kFusedCap) st->fused_over = 1;
+            stg[1] = b;
+        }
+        __syncthreads();
+        const int b = stg[1];
+        for (int i = tid; i < n; i += BS)
+            if (b + i < kFusedCap) C[b + i] = stage[i];
+    };
     const int n4 = tile_n >> 2;
     auto at4 = [](int i, int j) { return Q ? j * Q + i : 4 * i + j; };   // doc 4 i + j
     auto at = [](int d) { return Q ? (d & 3) * Q + (d >> 2) : d; };
@@ -189,15 +226,16 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
                     for (int j = 0; j < 4; j++) {
                         const uint32_t v = __float_as_uint((float)((double)a[h][j] * scale));
                         const unsigned long long c = comp_key(v, d0 + j);
-                        append_candidates(i < n4 && c >= bound, c, st, C);
+                        put(i < n4 && c >= bound, c);
                     }
                 }
             }
             for (int i = (n4 << 2) + tid; i < tile_n; i += BS) {
                 const uint32_t v = __float_as_uint((float)((double)acc[at(i)] * scale));
                 const unsigned long long c = comp_key(v, (uint32_t)(base + i));
-                append_candidates(c >= bound, c, st, C);
+                put(c >= bound, c);
             }
+            drain();
             return;
         }
     }
@@ -215,7 +253,7 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const unsigned long long c = comp_key(v[j], d0 + j);
-                append_candidates(c >= bound, c, st, C);
+                put(c >= bound, c);
             }
         }
     };
@@ -295,8 +333,9 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
         if (write) Sq[i] = v;
         const unsigned long long c = comp_key(v, (uint32_t)(base + i));
         if (count) atomicAdd(&hist[(c >> fs) & (kHistBins - 1)], 1u);
-        if (append) append_candidates(c >= bound, c, st, C);
+        if (append) put(c >= bound, c);
     }
+    drain();
     if (!count) return;
     __syncthreads();
     for (int b = tid; b < kHistBins; b += BS)
@@ -357,6 +396,7 @@ struct TileShared {
     unsigned long long fl_bound;
     double fl_scale;
     int fl_fused, fl_over, fl_shift;
+    int stg[2];  // the flush's candidate stage: count, base
 };
 static_assert(kMaxQueryNnz <= 512 && kMaxQueryNnz % kWave == 0, "segment setup: one thread per query term");
 
@@ -553,7 +593,10 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         sh.fl_scale = fl_scale;
     }
     __syncthreads();
-    if (wave == 0) {
+    {
+        // Every wavefront computes the chunk prefix of all segments (lane l: segments
+        // 4 l .. 4 l + 3) and writes its eighth of the chunk table; wavefront 0 also stores
+        // the prefix.
         int c[4];
         int s = 0;
 #pragma unroll
@@ -573,18 +616,17 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
         }
         // Chunk table: during accumulation the histogram's LDS holds the segment index
         // of every chunk (one byte each), so a wavefront finds its chunk's segment with
-        // one LDS read; tiles with more chunks than it holds fall back to a search. The
-        // lane that owns a segment writes its entries here, with the prefix at hand.
+        // one LDS read; tiles with more chunks than it holds fall back to a search.
         uint8_t* t8 = reinterpret_cast<uint8_t*>(hist);
         const bool table = total <= kHistBins * 4;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            sh.seg_cpre[lane * 4 + u] = run;
+            if (wave == 0) sh.seg_cpre[lane * 4 + u] = run;
             if (table)
-                for (int j = 0; j < c[u]; j++) t8[run + j] = (uint8_t)(lane * 4 + u);
+                for (int j = wave; j < c[u]; j += NW) t8[run + j] = (uint8_t)(lane * 4 + u);
             run += c[u];
         }
-        if (lane == 0) sh.seg_cpre[kMaxQueryNnz] = total;
+        if (tid == 0) sh.seg_cpre[kMaxQueryNnz] = total;
     }
     __syncthreads();
 
@@ -944,11 +986,16 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     }
     __syncthreads();
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
+    if (tid == 0) sh.stg[0] = 0;
     __syncthreads();
     // Fused filtering (the non-seed tiles of a query whose seed bound is set): append while
     // flushing, no appends once past the cap, and no score row for fp32 and uint8 (bf16 keeps
     // them for its band check). A query that falls back gets its rows from phase 3.
     SelState* st = state + ql;
+    // the flush's candidate stage: the histogram's LDS when the flush does not count, else the
+    // segment starts (the segment table is not read once the adds are done)
+    unsigned long long* stage_hist = reinterpret_cast<unsigned long long*>(hist);
+    unsigned long long* stage_seg = reinterpret_cast<unsigned long long*>(sh.seg_beg);
     const bool fused_q = phase == 2 && sh.fl_fused == 1;
     const bool app = fused_q && !sh.fl_over;
     const bool write = !fused_q || P == kBF16;
@@ -958,7 +1005,8 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     const bool count = !(fused_q && P != kBF16);
     flush_tile<BS, AF, (QD ? TILE / 4 : 0)>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, sh.fl_shift,
                        sh.fl_scale, hist1 + (int64_t)ql * kHistBins, app, app ? sh.fl_bound : 0ull, st,
-                       cand + (int64_t)ql * kCandCap, write, count);
+                       cand + (int64_t)ql * kCandCap, write, count, sh.stg, count ? stage_seg : stage_hist,
+                       count ? kMaxQueryNnz : kHistBins / 2);
 }
 
 // Per-query form: grid (tiles, queries), the tiles of one query are consecutive
