@@ -147,12 +147,15 @@ __device__ __forceinline__ void append_candidates(bool take, unsigned long long 
 // Q: 0 for a plain tile (doc d in accumulator d); else a tile in quarters (doc d in
 // accumulator (d % 4) * Q + d / 4, Q = tile size / 4), as the four-postings-per-lane loads of
 // score_tile leave it.
-// stg (optional): two LDS words, a stage count (0 on entry) and a base, and an LDS stage of
-// stage_cap entries. With it, a flush that appends stages its candidates and takes one range
-// of the query's buffer for all of them at the end (one global atomic per tile instead of one
-// per wavefront and hit, whose round trips otherwise hold up the tile's last wavefront);
-// candidates past the stage go to the buffer directly.
-template <int BS, int AF, int Q = 0>
+// stg (optional): 2 + BS / 64 LDS words (a base, unused, and a count per wavefront) and an LDS
+// stage of stage_cap entries. With it, a flush that appends stages its candidates, each
+// wavefront in its own slice with its count in a scalar register (no LDS round trip per hit),
+// and takes one range of the query's buffer for all of them at the end (one global atomic per
+// tile instead of one per wavefront and hit, whose round trips otherwise hold up the tile's
+// last wavefront); candidates past a wavefront's slice go to the buffer directly.
+// TD: the tile's size in docs (0: not known here). With it, the scan's read-ahead rounds stay
+// inside the tile by construction and are issued without a per-read guard.
+template <int BS, int AF, int Q = 0, int TD = 0>
 __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, int tile_n, int64_t base, uint32_t* Sq,
                                            int fs, double scale, uint32_t* hist_out, bool append,
                                            unsigned long long bound, SelState* st, unsigned long long* C,
@@ -160,6 +163,14 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
                                            unsigned long long* stage = nullptr, int stage_cap = 0) {
     const int tid = threadIdx.x;
     const bool staged = stg != nullptr && append;
+    constexpr int NWF = BS / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int per_w = stage_cap / NWF;
+    unsigned long long* my_stage = stage + wv * per_w;
+    // The wavefront's staged candidates. Lanes that leave a scan loop early keep an old value,
+    // so the count is always taken from the first active lane: every loop here keeps a prefix
+    // of the lanes active, so that is lane 0, which takes part in every append.
+    int w_cnt = 0;
     auto put = [&](bool take, unsigned long long c) {
         if (!staged) {
             append_candidates(take, c, st, C);
@@ -167,28 +178,36 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
         }
         const unsigned long long m = __ballot(take);
         if (m == 0) return;
-        const int lane = tid & (kWave - 1);
-        const int leader = __ffsll((long long)__ballot(1)) - 1;
-        int slot = 0;
-        if (lane == leader) slot = atomicAdd(&stg[0], __popcll(m));
-        slot = __shfl(slot, leader, kWave) + __popcll(m & ((1ull << lane) - 1ull));
-        if (take && slot < stage_cap) stage[slot] = c;
-        append_candidates(take && slot >= stage_cap, c, st, C);  // past the stage: to the buffer directly
+        const int wc = __builtin_amdgcn_readfirstlane(w_cnt);
+        const int slot = wc + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (take && slot < per_w) my_stage[slot] = c;
+        const int pc = __popcll(m);
+        if (wc + pc > per_w) append_candidates(take && slot >= per_w, c, st, C);  // past the slice
+        w_cnt = min(wc + pc, per_w);
     };
     auto drain = [&]() {
         if (!staged) return;
+        const int wc = __builtin_amdgcn_readfirstlane(w_cnt);
+        if ((tid & (kWave - 1)) == 0) stg[2 + wv] = wc;
         __syncthreads();
-        const int n = min(stg[0], stage_cap);
+        int n = 0, off = 0;
+#pragma unroll
+        for (int w = 0; w < NWF; w++) {
+            const int cw = stg[2 + w];
+            off += w < wv ? cw : 0;
+            n += cw;
+        }
         if (n == 0) return;
         if (tid == 0) {
             const int b = atomicAdd(&st->n_cand, n);
             if (b + n > kFusedCap) st->fused_over = 1;
-            stg[1] = b;
+            stg[0] = b;
         }
         __syncthreads();
-        const int b = stg[1];
-        for (int i = tid; i < n; i += BS)
-            if (b + i < kFusedCap) C[b + i] = stage[i];
+        const int b = stg[0] + off;
+        for (int i = tid & (kWave - 1); i < wc; i += kWave)
+            if (b + i < kFusedCap) C[b + i] = my_stage[i];
     };
     const int n4 = tile_n >> 2;
     auto at4 = [](int i, int j) { return Q ? j * Q + i : 4 * i + j; };   // doc 4 i + j
@@ -204,8 +223,10 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
             const double sb = (double)__uint_as_float((uint32_t)(bound >> 32));
             const unsigned long long t_lo = (unsigned long long)fmax(0.0, floor(sb * (1.0 - 0x1p-22) / scale));
             const unsigned long long* acc = (const unsigned long long*)acc_v;
-            // two rounds of reads issued before the first test: one LDS round trip (which the
-            // other workgroup's atomics make long) per two
+            // two rounds of reads issued before the first test (one LDS round trip per two); in a
+            // tile of TD docs every round reads inside the tile (TD / 4 is a multiple of 2 BS), so
+            // the reads need no guard (rounds past a short last tile's end are not tested)
+            constexpr bool FULL = TD > 0 && (TD / 4) % (2 * BS) == 0;
             constexpr int R = 2;
             for (int i0 = tid; i0 < n4; i0 += R * BS) {
                 unsigned long long a[R][4];
@@ -213,7 +234,7 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
                 for (int h = 0; h < R; h++) {
                     const int i = i0 + h * BS;
 #pragma unroll
-                    for (int j = 0; j < 4; j++) a[h][j] = i < n4 ? acc[at4(i, j)] : 0ull;
+                    for (int j = 0; j < 4; j++) a[h][j] = (FULL || i < n4) ? acc[at4(i, j)] : 0ull;
                 }
 #pragma unroll
                 for (int h = 0; h < R; h++) {
@@ -260,20 +281,20 @@ __device__ __forceinline__ void flush_tile(const void* acc_v, uint32_t* hist, in
     int i_first = 0;
     if constexpr (Q != 0 && (AF == kAccInt || AF == kAccFx32)) {
         // a tile in quarters: 16 docs 16 g .. 16 g + 15 per lane, one 16-byte read from each
-        // quarter (word 4 g + m of quarter j is doc 16 g + 4 m + j)
-        // (two rounds of reads issued before the first test)
+        // quarter (word 4 g + m of quarter j is doc 16 g + 4 m + j); two rounds of reads issued
+        // before the first test where a tile's Q / 4 groups are a multiple of 2 BS, else one.
+        // Every round then reads inside the tile (no guard per read); a round past a short
+        // last tile's end is read but not tested.
         const uint32_t* acc = (const uint32_t*)acc_v;
         const int n16 = tile_n >> 4;
-        constexpr int IT = 2;
+        constexpr int IT = (Q / 4) % (2 * BS) == 0 ? 2 : 1;
         for (int g0 = tid; g0 < n16; g0 += IT * BS) {
             uint4 r[IT][4];
 #pragma unroll
             for (int it = 0; it < IT; it++) {
                 const int g = g0 + it * BS;
 #pragma unroll
-                for (int j = 0; j < 4; j++)
-                    r[it][j] = g < n16 ? *reinterpret_cast<const uint4*>(acc + j * Q + 4 * g)
-                                       : make_uint4(0u, 0u, 0u, 0u);
+                for (int j = 0; j < 4; j++) r[it][j] = *reinterpret_cast<const uint4*>(acc + j * Q + 4 * g);
             }
 #pragma unroll
             for (int it = 0; it < IT; it++) {
@@ -396,7 +417,7 @@ struct TileShared {
     unsigned long long fl_bound;
     double fl_scale;
     int fl_fused, fl_over, fl_shift;
-    int stg[2];  // the flush's candidate stage: count, base
+    int stg[2 + 512 / kWave];  // the flush's candidate stage: base, unused, a count per wavefront
 };
 static_assert(kMaxQueryNnz <= 512 && kMaxQueryNnz % kWave == 0, "segment setup: one thread per query term");
 
@@ -986,7 +1007,6 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     }
     __syncthreads();
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
-    if (tid == 0) sh.stg[0] = 0;
     __syncthreads();
     // Fused filtering (the non-seed tiles of a query whose seed bound is set): append while
     // flushing, no appends once past the cap, and no score row for fp32 and uint8 (bf16 keeps
@@ -1003,7 +1023,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     // only: its selection needs no more, and if it falls back, phase 3 scores these tiles
     // again and counts them then (bf16 has no phase 3 and counts here).
     const bool count = !(fused_q && P != kBF16);
-    flush_tile<BS, AF, (QD ? TILE / 4 : 0)>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, sh.fl_shift,
+    flush_tile<BS, AF, (QD ? TILE / 4 : 0), TILE>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, sh.fl_shift,
                        sh.fl_scale, hist1 + (int64_t)ql * kHistBins, app, app ? sh.fl_bound : 0ull, st,
                        cand + (int64_t)ql * kCandCap, write, count, sh.stg, count ? stage_seg : stage_hist,
                        count ? kMaxQueryNnz : kHistBins / 2);
