@@ -531,7 +531,7 @@ def main():
     written = None
     tile_docs = args.tile_docs or (8192 if args.precision == "fp32" else 16384)
     n_tiles = (n_docs + tile_docs - 1) // tile_docs
-    if (not args.no_fused and args.kernel in ("tiled", "shared", "group") and args.precision != "bf16" and nq >= 32
+    if (not args.no_fused and args.kernel in ("tiled", "shared", "group") and nq >= 32
             and args.k <= 1024 and n_tiles >= 16):
         # fused candidate filtering: score rows of the seed tiles (every 8th) only
         written = sum(min(tile_docs, n_docs - t * tile_docs) for t in range(0, n_tiles, 8))

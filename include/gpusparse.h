@@ -410,7 +410,8 @@ int32_t gs_autotune(gs_index index, gs_batch batch, void* workspace, size_t work
  *       report GS_ECAPACITY for it;
  *   [4] rows scored again: 0 no, 1 fallback of fused candidate filtering,
  *       2 wide range (fixed-point error too large for the k-th score: every
- *       tile summed again in fp64);
+ *       tile summed again in fp64), 3 (GS_BF16) the error band reached below
+ *       the fused candidates: the other tiles' rows scored for the band pass;
  *   [5] 1 if fused candidate filtering produced the candidates;
  *   [6] 64-posting blocks skipped by pruning (opts.prune);
  *   [7] 0.

@@ -1309,12 +1309,12 @@ int32_t enqueue_search(gs_index ix, gs_batch b, int32_t nq, const Workspace& ws,
         if (e == hipSuccess) {
             SpanRecorder rec(timing ? 1 : -1, s);
             // Between the two first-digit selection passes: the rows of the listed queries.
-            // Fused fp32 / uint8 queries that fell back get their non-seed tiles scored (phase 3);
+            // Fused queries that fell back get their non-seed tiles scored (phase 3);
             // fixed-point queries found wide range get every tile scored in fp64 (phase 4).
             const bool doc_tiled =
                 so.kernel == GS_KERNEL_TILED || so.kernel == GS_KERNEL_SHARED || so.kernel == GS_KERNEL_GROUP;
             const bool fixed = doc_tiled && ix->precision != kU8;
-            const bool phase3 = so.seed_stride > 0 && ix->precision != kBF16;
+            const bool phase3 = so.seed_stride > 0;
             const int acc = ix->precision == kU8 ? kAccInteger : (doc_tiled ? kAccFixed : kAccFloat);
             e = launch_select(ix->dev, b->dev, q0, n, ws, out_ids, out_scores, b->diag, s, acc, so.tile_shift,
                               so.seed_stride, phase3 ? &so : nullptr, fixed);

@@ -186,8 +186,9 @@ struct ScoreOpts {
 // Doc tiles of a scoring launch: phase 0 all tiles, phase 1 the seed tiles
 // (multiples of stride), phase 2 the others, phase 3 the others again for the
 // queries that fell back from fused filtering (their rows), phase 4 all tiles
-// again for the wide-range queries (fp64 accumulation). v is the launch's tile
-// index.
+// again for the wide-range queries (fp64 accumulation), phase 5 the others again
+// for the bf16 queries whose error band reaches below their fused candidates
+// (their rows, for the band pass). v is the launch's tile index.
 __host__ __device__ inline int64_t phase_tiles(int phase, int stride, int64_t n_tiles) {
     if (phase == 0 || phase == 4) return n_tiles;
     const int64_t seeds = (n_tiles + stride - 1) / stride;

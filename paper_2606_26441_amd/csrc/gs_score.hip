@@ -492,6 +492,7 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     if (qb.k[q] == 0) return;  // nothing is selected for it (also every padding slot of a batch)
     if (phase == 3 && state[ql].rescore != 1) return;  // only the queries that fell back
     if (phase == 4 && state[ql].rescore != 2) return;  // only the wide-range queries
+    if (phase == 5 && state[ql].rescore != 3) return;  // only the bf16 band passes of fused queries
     // What the flush needs of the query: one thread loads it now, so that the latency passes
     // under the setup, and leaves it in LDS (registers are what the accumulation runs short
     // of). The state is set before this launch; the cap flag may be set during it by other
@@ -1009,8 +1010,9 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     for (int i = tid; i < kHistBins; i += BS) hist[i] = 0u;
     __syncthreads();
     // Fused filtering (the non-seed tiles of a query whose seed bound is set): append while
-    // flushing, no appends once past the cap, and no score row for fp32 and uint8 (bf16 keeps
-    // them for its band check). A query that falls back gets its rows from phase 3.
+    // flushing, no appends once past the cap, and no score row. A query that falls back gets
+    // its rows from phase 3; a bf16 query whose error band reaches below its candidates gets
+    // them from phase 5, before the band pass.
     SelState* st = state + ql;
     // the flush's candidate stage: the histogram's LDS when the flush does not count, else the
     // segment starts (the segment table is not read once the adds are done)
@@ -1018,11 +1020,11 @@ __device__ __forceinline__ void score_tile(const DevIndex& ix, const DevBatch& q
     unsigned long long* stage_seg = reinterpret_cast<unsigned long long*>(sh.seg_beg);
     const bool fused_q = phase == 2 && sh.fl_fused == 1;
     const bool app = fused_q && !sh.fl_over;
-    const bool write = !fused_q || P == kBF16;
-    // The first-digit histogram of a fused fp32/uint8 query keeps the seed tiles' counts
-    // only: its selection needs no more, and if it falls back, phase 3 scores these tiles
-    // again and counts them then (bf16 has no phase 3 and counts here).
-    const bool count = !(fused_q && P != kBF16);
+    const bool write = !fused_q;
+    // The first-digit histogram of a fused query keeps the seed tiles' counts only: its
+    // selection needs no more, and if it falls back, phase 3 scores these tiles again and
+    // counts them then.
+    const bool count = !fused_q;
     flush_tile<BS, AF, (QD ? TILE / 4 : 0), TILE>(lds, hist, tile_n, base, S + (int64_t)ql * ld + base, sh.fl_shift,
                        sh.fl_scale, hist1 + (int64_t)ql * kHistBins, app, app ? sh.fl_bound : 0ull, st,
                        cand + (int64_t)ql * kCandCap, write, count, sh.stg, count ? stage_seg : stage_hist,
@@ -1087,8 +1089,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int x = (int)(blockIdx.x & 7);
     const int64_t n_tiles = phase_tiles(phase, stride, (ix.n_docs + (1 << TS) - 1) >> TS);
     const int64_t tiles_x = n_tiles > x ? (n_tiles - x + 7) / 8 : 0;
-    // phase 3 covers only the queries that fell back from fused filtering (usually none)
-    const int nq = phase == 3 ? (int)counters[8] : qt;
+    // phases 3 and 5 cover only the listed queries (fused filtering's fallbacks, bf16 band
+    // passes; usually none)
+    const bool listed = phase == 3 || phase == 5;
+    const int nq = listed ? (int)counters[8] : qt;
     const int64_t items = tiles_x * nq;
     for (;;) {
         if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(&counters[x], 1u);
@@ -1096,7 +1100,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int64_t item = item_sh;
         if (item >= items) break;
         const int64_t tile = phase_tile(phase, stride, x + 8 * (item / nq));
-        const int ql = phase == 3 ? rescore_list[item % nq] : order[item % nq];
+        const int ql = listed ? rescore_list[item % nq] : order[item % nq];
         // uint8 weights: four postings per lane and load (measured +10 %; the fixed-point forms,
         // with more arithmetic per posting, ran 4-6 % slower that way)
         score_tile<P, TS, CH, false, false, false, (P == kU8 && CH % 256 == 0)>(ix, qb, q0, tile, ql, S, ld, hist1,
@@ -1333,8 +1337,10 @@ __global__ __launch_bounds__(group_size<P>() * kMaxQueryNnz) __attribute__((amdg
             SelState* st = state + ql;
             const bool fused_q = phase == 2 && st->fused == 1;
             const bool app = fused_q && !st->fused_over;
-            const bool write = !fused_q || P == kBF16;
-            const bool count = !(fused_q && P != kBF16);
+            // as in score_tile: a fused query writes no row and counts no tile here; its
+            // fallback (phase 3) or bf16 band pass (phase 5) scores these tiles again
+            const bool write = !fused_q;
+            const bool count = !fused_q;
             flush_tile<BS, AF>(lds + m * TILE * AW, hist, tile_n, base, S + (int64_t)ql * ld + base,
                                qb.first_shift[ql], FX ? qb.q_scale[ql] : 1.0, hist1 + (int64_t)ql * kHistBins, app,
                                app ? st->bound : 0ull, st, cand + (int64_t)ql * kCandCap, write, count);
@@ -1553,7 +1559,7 @@ hipError_t launch_tiled_one(const DevIndex& ix, const DevBatch& qb, int32_t q0, 
                 return hipSuccess;
             }
         }
-        if (phase == 3) {
+        if (phase == 3 || phase == 5) {
             hipLaunchKernelGGL((k_score_listed<P, TS, CH>), dim3((unsigned)n_tiles, 1u), dim3(512), lds, s, ix, qb, q0,
                                ws.scores, ld, ws.hist1, phase, stride, ws.state, ws.cand, (const uint32_t*)ws.counters,
                                (const int32_t*)ws.rescore_list);

@@ -25,14 +25,15 @@
 // bf16 form: k_final also derives the error band of the k-th approximate score
 // and rescores every candidate in the band in fp64 from the fp32 forward rows
 // (ascending term order); k_band_filter / k_band_final handle the rare case in
-// which the band reaches below the candidate threshold.
+// which the band reaches below the candidate threshold (a fused query first gets
+// the rows of its other tiles, scoring phase 5).
 //
 // Fused candidate filtering (doc-tiled kernels, searches of 32+ queries): the
 // seed tiles (every 8th doc tile) are scored first; k_seed_bound / k_seed_hist /
 // k_seed_refine derive from them a lower bound of each query's k-th composite
 // (a 22-bit bucket edge); the other tiles append every composite at or above it
-// while they are scored (fp32 and uint8 then write no score rows for them and do
-// not count them in the histogram), and step 4 scans only the seed tiles.
+// while they are scored (then writing no score rows for them and not counting
+// them in the histogram), and step 4 scans only the seed tiles.
 // k_select_first falls back to the full row (no bound, too many appended, or a
 // refinement needed); such a query is listed, its other tiles are scored and
 // counted again, and a second k_select_first pass redoes its step 2 from the
@@ -157,10 +158,8 @@ __global__ __launch_bounds__(64) void k_select_first(DevBatch qb, int32_t q0, in
     if (st->fused == 1 && (st->resolved != 1 || st->fused_over || (int64_t)st->n_cand + kept > kCandCap)) {
         st->fused = 0;
         st->n_cand = 0;
-        if (precision != kBF16) {  // its non-seed rows were not written: score them again
-            st->rescore = 1;
-            rescore_list[atomicAdd(&counters[8], 1u)] = ql;
-        }
+        st->rescore = 1;  // its non-seed rows were not written: score them again
+        rescore_list[atomicAdd(&counters[8], 1u)] = ql;
     }
 }
 
@@ -567,7 +566,8 @@ template <int P>
 __global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_t q0, SelState* __restrict__ state,
                                                 const unsigned long long* __restrict__ cand,
                                                 double* __restrict__ band_s, int32_t* __restrict__ band_id,
-                                                int32_t* __restrict__ out_ids, void* __restrict__ out_scores, int acc) {
+                                                int32_t* __restrict__ out_ids, void* __restrict__ out_scores, int acc,
+                                                uint32_t* __restrict__ counters, int32_t* __restrict__ rescore_list) {
     __shared__ unsigned long long sel[kMaxK];
     __shared__ uint32_t hist[256];
     __shared__ int sh_d, sh_cnt;
@@ -703,6 +703,10 @@ __global__ __launch_bounds__(1024) void k_final(DevIndex ix, DevBatch qb, int32_
             if (tid == 0) {
                 st->need_band_pass = 1;
                 st->tau = tau;
+                if (st->fused == 1) {  // its other tiles wrote no rows: score them for the band pass
+                    st->rescore = 3;
+                    rescore_list[atomicAdd(&counters[8], 1u)] = ql;
+                }
             }
             return;
         }
@@ -850,17 +854,17 @@ hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int
             case kFP32:
                 hipLaunchKernelGGL(k_final<kFP32>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
                                    (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores,
-                                   acc);
+                                   acc, ws.counters, ws.rescore_list);
                 break;
             case kU8:
                 hipLaunchKernelGGL(k_final<kU8>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
                                    (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores,
-                                   acc);
+                                   acc, ws.counters, ws.rescore_list);
                 break;
             default:
                 hipLaunchKernelGGL(k_final<kBF16>, dim3(qt), dim3(1024), 0, s, ix, qb, q0, ws.state,
                                    (const unsigned long long*)ws.cand, ws.band_s, ws.band_id, out_ids, out_scores,
-                                   acc);
+                                   acc, ws.counters, ws.rescore_list);
                 break;
         }
         GS_CHECK_LAUNCH("k_final");
@@ -880,6 +884,10 @@ hipError_t launch_select(const DevIndex& ix, const DevBatch& qb, int32_t q0, int
     hipError_t e = final_pass();
     if (e != hipSuccess) return e;
     if (ix.precision == kBF16) {
+        if (phase3) {  // fused queries whose band reaches below their candidates: the other tiles' rows
+            e = launch_score_tiled(ix, qb, q0, qt, *phase3, ws, s, 5);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(k_band_filter, grid_scan, dim3(512), 0, s, q0, N, (const uint32_t*)ws.scores, ws.ld, per,
                            ws.state, ws.band_id);
         GS_CHECK_LAUNCH("k_band_filter");

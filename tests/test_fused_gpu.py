@@ -95,6 +95,27 @@ def test_fused_fallback_on_massive_ties(precision):
     idx.close()
 
 
+def test_fused_bf16_band_pass_scores_the_other_tiles():
+    # all weights 1 and one-term queries: every doc of the term ties at the k-th score, among
+    # the seed tiles too, so the seed bound sits on that score and the bf16 error band below
+    # the k-th approximate score reaches under it. A fused query then has no rows for its other
+    # tiles: they are scored for the band pass (diagnostics word 4 = 3), and the result must
+    # equal the row scan's and the oracle's
+    gs, torch = _gs()
+    rng = np.random.default_rng(66)
+    docs = random_rows(rng, 300_000, 100, 1, 8, weight_fn=lambda r, n: np.ones(n))
+    qs = random_rows(rng, 40, 100, 1, 1, weight_fn=lambda r, n: np.ones(n))
+    idx = gs.Index.from_rows(docs, "bf16")
+    for kernel in ("tiled", "shared", "group"):
+        a = _search(gs, torch, idx, qs, 10, 10, kernel, True)
+        b = _search(gs, torch, idx, qs, 10, 10, kernel, False)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), kernel
+        assert np.any(a[2][:, 4] == 3), "%s: no band pass took the other tiles' rows" % kernel
+        assert np.all(b[2][:, 4] != 3), kernel
+    check_batch("bf16", docs, qs.subset(np.arange(6)), a[0][:6], a[1][:6], 10, what="bf16 band rows")
+    idx.close()
+
+
 def test_fused_graph_replays(data):
     gs, torch = _gs()
     docs, qs = data

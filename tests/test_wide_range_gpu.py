@@ -93,14 +93,15 @@ def test_wide_range_weights_meet_the_rules(data, precision, kernel, fused):
     check_batch(precision, docs, qs, ids.cpu().numpy(), sc.cpu().numpy(), ks, what="%s %s" % (precision, kernel))
     if kernel in ("tiled", "shared", "group"):
         # The fixed-point kernels sum the wide-range queries again in fp64. Without fused
-        # filtering no other query takes that pass. With it, an fp32 query is checked against
-        # the k-th score of the seed tiles (a lower bound): query 4 ({A, B}, k = 300) has fewer
-        # than 300 A docs there, so its bound falls among the B-only docs and it may take the
-        # pass too (the check is conservative, the result the same).
+        # filtering no other query takes that pass. With it, a query is checked against the
+        # k-th score of the seed tiles (a lower bound; a fused query counts no other tile):
+        # query 4 ({A, B}, k = 300) has fewer than 300 A docs there, so its bound falls among
+        # the B-only docs and it may take the pass too (the check is conservative, the result
+        # the same).
         for q, wd in enumerate(wide):
             if wd is True:
                 assert diag[q, 4] == 2, "query %d was not summed in fp64" % q
-            elif wd is False and not (fused and precision == "fp32" and q == 4):
+            elif wd is False and not (fused and q == 4):
                 assert diag[q, 4] != 2, "query %d was summed in fp64 without need" % q
     else:
         assert np.all(diag[:, 4] != 2), "fp32-accumulating kernels have no fp64 pass"
