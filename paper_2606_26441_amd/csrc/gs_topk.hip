@@ -209,13 +209,23 @@ __global__ __launch_bounds__(512) void k_seed_hist(int64_t N, const uint32_t* __
     const unsigned long long mask = (1ull << (shift - nshift)) - 1ull;
     const int64_t d0 = ((int64_t)blockIdx.x * stride) << tile_shift, d1 = min(N, d0 + (1ll << tile_shift));
     const uint32_t* Sq = S + (int64_t)ql * ld;
-    for (int64_t d = d0 + 4 * tid; d < d1; d += 4 * 512) {
-        const uint4 v = *reinterpret_cast<const uint4*>(Sq + d);  // d + 3 < ld: rows are padded to 64
-        const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+    // four rounds of 16-byte loads before the first count (a lane past the tile reads its last
+    // aligned four scores and counts nothing)
+    constexpr int R = 4;
+    const int64_t last = (d1 - 1) & ~3ll;  // d + 3 < ld: rows are padded to 64
+    for (int64_t d0r = d0 + 4 * tid; d0r < d1; d0r += 4 * 512 * R) {
+        uint4 v[R];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const unsigned long long c = comp_key(vs[j], (uint32_t)(d + j));
-            if (d + j < d1 && (c >> shift) == want) atomicAdd(&hist[(c >> nshift) & mask], 1u);
+        for (int r = 0; r < R; r++) v[r] = *reinterpret_cast<const uint4*>(Sq + min(d0r + r * 2048, last));
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const int64_t d = d0r + r * 2048;
+            const uint32_t vs[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const unsigned long long c = comp_key(vs[j], (uint32_t)(d + j));
+                if (d + j < d1 && (c >> shift) == want) atomicAdd(&hist[(c >> nshift) & mask], 1u);
+            }
         }
     }
     __syncthreads();
@@ -330,23 +340,33 @@ __global__ __launch_bounds__(512) void k_filter(int32_t q0, int64_t N, const uin
     const int64_t b0 = (int64_t)blockIdx.x * per_block, b1 = min(N, b0 + per_block);  // per_block % 256 == 0
     const uint32_t* Sq = S + (int64_t)ql * ld;
     unsigned long long* C = cand + (int64_t)ql * kCandCap;
+    // Four rounds of 16-byte loads are issued before the first test (a single load in flight
+    // per lane left the scan at about half the HBM rate). A lane past the range reads the
+    // range's last aligned four scores instead (no branch around the load) and tests nothing.
     auto scan = [&](int64_t d0, int64_t d1) {  // d0 % 256 == 0
-        for (int64_t wb = d0 + (int64_t)wave * kWave * 4; wb < d1; wb += 512 * 4) {
-            const int64_t d = wb + (int64_t)lane * 4;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (d < d1) v = *reinterpret_cast<const uint4*>(Sq + d);  // d + 3 < ld: rows are padded to 64
-            const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+        constexpr int R = 4;
+        const int64_t last = (d1 - 1) & ~3ll;  // d + 3 < ld: rows are padded to 64
+        for (int64_t wb = d0 + (int64_t)wave * kWave * 4; wb < d1; wb += 512 * 4 * R) {
+            uint4 v[R];
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const unsigned long long c = comp_key(vs[j], (uint32_t)(d + j));
-                const bool take = d + j < d1 && c >= lo;
-                const unsigned long long m = __ballot(take);
-                if (m == 0) continue;
-                int slot = 0;
-                if (lane == 0) slot = atomicAdd(&n_stage, __popcll(m));
-                slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
-                if (take && slot < kFilterStage) stage[slot] = c;
-                append_global(st, C, take && slot >= kFilterStage, c, lane);
+            for (int r = 0; r < R; r++)
+                v[r] = *reinterpret_cast<const uint4*>(Sq + min(wb + r * 2048 + (int64_t)lane * 4, last));
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const int64_t d = wb + r * 2048 + (int64_t)lane * 4;
+                const uint32_t vs[4] = {v[r].x, v[r].y, v[r].z, v[r].w};
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const unsigned long long c = comp_key(vs[j], (uint32_t)(d + j));
+                    const bool take = d + j < d1 && c >= lo;
+                    const unsigned long long m = __ballot(take);
+                    if (m == 0) continue;
+                    int slot = 0;
+                    if (lane == 0) slot = atomicAdd(&n_stage, __popcll(m));
+                    slot = __shfl(slot, 0, kWave) + __popcll(m & ((1ull << lane) - 1ull));
+                    if (take && slot < kFilterStage) stage[slot] = c;
+                    append_global(st, C, take && slot >= kFilterStage, c, lane);
+                }
             }
         }
     };
