@@ -60,7 +60,7 @@ def parse():
                     help="precisions for the 4,096-query uneven batch (autotuned, graph vs plain), or 'none'")
     ap.add_argument("--batched-queries", type=int, default=4096)
     ap.add_argument("--top10", type=int, default=1, help="also time every form at top-10 (1) or not (0)")
-    ap.add_argument("--serving", default="200,800,2000,16000", help="Poisson arrival rates (QPS) for the serving loop, or 'none'")
+    ap.add_argument("--serving", default="200,800,2000,16000,20000", help="Poisson arrival rates (QPS) for the serving loop, or 'none'")
     ap.add_argument("--serving-seconds", type=float, default=30.0, help="duration of each rate up to 2000 QPS")
     ap.add_argument("--serving-seconds-high", type=float, default=10.0, help="duration of each rate above 2000 QPS")
     ap.add_argument("--serving-budget-gib", type=float, default=8.0,
